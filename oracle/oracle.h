@@ -1,0 +1,75 @@
+/*
+ * Plain CPU oracle for the sector-tracking hot path (test infrastructure).
+ *
+ * ONLY tests/, __graft_entry__.smoke() and the cpu_baseline leg of bench.py
+ * may load or call this library.  It shares no code with the HIP path.
+ *
+ * Everything here works on ONE sector: hits in the sector-local frame, sorted
+ * by pad row, indices sector-local.  The floating-point functions exist in two
+ * builds of the same source: *_f32 (every + - * / sqrt rounded to nearest in
+ * binary32, no contraction) and *_f64 (the same sequence in binary64).
+ *
+ * Paper: Rohr, Gorbunov, Lindenstruth, "GPU-accelerated track reconstruction
+ * in the ALICE High Level Trigger" (arXiv:1712.09430), Sec. 2 (seeding by a
+ * cellular automaton, track following with a simplified Kalman filter).
+ */
+#ifndef CATPC_ORACLE_H
+#define CATPC_ORACLE_H
+#include <stdint.h>
+
+typedef struct {
+  float bz;             /* field, T */
+  float sigma_y;        /* cluster error in y, cm */
+  float sigma_z;        /* cluster error in z, cm */
+  float nf_win_y;       /* neighbour window half-width in y, cm */
+  float nf_win_z;       /* neighbour window half-width in z, cm */
+  float nf_chi2_max;    /* cut on the 3-point residual, cm^2 */
+  float tc_gate_nsigma; /* following gate in units of the predicted error */
+  int32_t tc_max_miss;  /* following stops after more consecutive misses than this */
+  int32_t min_hits;     /* tracklets with fewer hits are not flagged valid */
+  int32_t precision;    /* f32 build: 0 none, 1 refit SPD failures with FP64 covariance, 2 refit all */
+} oracle_params;
+
+/* tracklet flag bits */
+#define ORACLE_VALID 1
+#define ORACLE_STOP_SINPHI 2
+#define ORACLE_STOP_ARC 4
+#define ORACLE_SPD_FAIL 8
+#define ORACLE_REFIT64 16
+
+/* state vector layout used by the unit entry points (15 values):
+ * x, y, z, s=sin(phi), l=tan(lambda), q=q/pT,
+ * transverse covariance over (y, s, q): c_yy, c_sy, c_ss, c_qy, c_qs, c_qq,
+ * longitudinal covariance over (z, l): c_zz, c_lz, c_ll */
+
+#define ORACLE_DECL(SFX, REAL)                                                                     \
+  int32_t oracle_neighbours##SFX(int32_t n_rows, const float* row_x, int32_t n, const float* y,   \
+                                 const float* z, const int32_t* row, const oracle_params* p,       \
+                                 int32_t* link_up, int32_t* link_dn);                              \
+  int32_t oracle_tracklets##SFX(int32_t n_rows, const float* row_x, int32_t n, const float* y,    \
+                                const float* z, const int32_t* row, const int32_t* up_clean,       \
+                                int32_t n_start, const int32_t* start, const oracle_params* p,     \
+                                REAL* x_ref, REAL* param, REAL* cov, int32_t* row_hit,             \
+                                int32_t* start_row, int32_t* first_row, int32_t* last_row,         \
+                                int32_t* n_hits, int32_t* flags, int64_t* counters);               \
+  int32_t oracle_refit##SFX(int32_t n_rows, const float* row_x, int32_t n, const float* y,        \
+                            const float* z, int32_t n_trk, const int32_t* row_hit,                 \
+                            const int32_t* start_row, const oracle_params* p, REAL* x_ref,         \
+                            REAL* param, REAL* cov, int32_t* flags);                               \
+  int32_t oracle_init##SFX(const REAL* h0, const REAL* h1, const oracle_params* p, REAL* st);     \
+  int32_t oracle_propagate##SFX(REAL* st, REAL x1, const oracle_params* p);                       \
+  int32_t oracle_update##SFX(REAL* st, REAL my, REAL mz, const oracle_params* p);                 \
+  int32_t oracle_spd##SFX(const REAL* st);
+
+ORACLE_DECL(_f32, float)
+ORACLE_DECL(_f64, double)
+
+int32_t oracle_clean_links(int32_t n, const int32_t* link_up, const int32_t* link_dn,
+                           int32_t* up_clean, int32_t* dn_clean, uint8_t* is_start);
+
+int32_t oracle_refit_mixed(int32_t n_rows, const float* row_x, int32_t n, const float* y,
+                           const float* z, int32_t n_trk, const int32_t* row_hit,
+                           const int32_t* start_row, const oracle_params* p, float* x_ref,
+                           float* param, float* cov, int32_t* spd_ok);
+
+#endif

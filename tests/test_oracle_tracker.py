@@ -1,0 +1,184 @@
+"""Pins for the oracle's whole sector path (Sec. 2 items 1-2): noise-free
+tracks are found whole, seeds are disjoint and climb one row per link, the
+binary32 and binary64 modes agree within the stated tolerance, and fitted
+parameters scatter around the generated truth as their covariance says."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+P = oracle.Params()
+
+# Tolerance of binary32 parameters against the binary64 refit of the same hits:
+# y, z within 1e-3 cm; sin phi, tan lambda within 1e-4 relative (floor 1);
+# q/pT within 1e-4 relative (floor 0.1 GeV^-1) or, where q/pT is barely
+# measured, within 1 % of its own binary64 standard error (binary32 rounding of
+# residuals of coordinates up to 250 cm, times the large q/pT gain of short
+# tracklets, is then the limit, and it is far below the measurement error).
+TOL_ABS = np.array([1e-3, 1e-3, 0.0, 0.0, 0.0])
+TOL_REL = np.array([0.0, 0.0, 1e-4, 1e-4, 1e-4])
+TOL_FLOOR = np.array([1.0, 1.0, 1.0, 1.0, 0.1])
+
+
+def within_tolerance(p32, p64, cov64):
+    d = np.abs(p32.astype(np.float64) - p64)
+    lim = TOL_ABS + TOL_REL * np.maximum(np.abs(p64), TOL_FLOOR)
+    lim[..., 4] = np.maximum(lim[..., 4], 0.01 * np.sqrt(cov64[..., 14]))
+    return np.all(d <= lim, axis=-1), d
+
+
+def test_noise_free_separated_tracks_are_found_whole():
+    tracks = {"q": [1, -1, 1, -1, 1], "pt": [8.0, 3.0, 1.5, 0.8, 0.4], "eta": [0.05, 0.25, 0.45, 0.65, 0.85],
+              "phi0": [math.radians(a) for a in (3.0, 7.0, 11.0, 14.0, 17.0)]}
+    b = synth.tracks_workload(tracks, sigma=0.0, noise_frac=0.0)
+    s = b.sector(0)
+    o = oracle.track_sector(s["y"], s["z"], s["row"], b.row_x, P, "f32")
+    lab = s["label"]
+    found = {}
+    for t in range(len(o["start"])):
+        rh = o["row_hit"][t]
+        hits = rh[rh >= 0]
+        ls = set(lab[hits].tolist())
+        assert len(ls) == 1
+        found.setdefault(ls.pop(), []).append(set(hits.tolist()))
+    for L in range(5):
+        mine = set(np.flatnonzero(lab == L).tolist())
+        if len(mine) < 10:
+            continue
+        assert L in found and len(found[L]) == 1
+        assert found[L][0] == mine
+    assert np.all(o["flags"] & oracle.VALID)
+
+
+def test_seed_invariants_on_a_full_sector():
+    b = synth.sector_workload(seed=2)
+    s = b.sector(0)
+    o = oracle.track_sector(s["y"], s["z"], s["row"], b.row_x, P, "f32")
+    row = s["row"]
+    uc, dc = o["up_clean"], o["dn_clean"]
+    ok = uc >= 0
+    assert np.all(row[uc[ok]] == row[ok] + 1)
+    ok = o["link_dn"] >= 0
+    assert np.all(row[o["link_dn"][ok]] == row[ok] - 1)
+    # chains from the start hits are disjoint
+    seen = set()
+    for h in o["start"]:
+        n = 0
+        while h >= 0:
+            assert h not in seen
+            seen.add(int(h))
+            h = uc[h]
+            n += 1
+        assert n >= 3
+    assert np.all(np.diff(o["start"]) > 0)
+    # the start hit and its chain lead every tracklet
+    for t, h in enumerate(o["start"]):
+        assert o["row_hit"][t, row[h]] == h and o["start_row"][t] == row[h]
+        assert o["first_row"][t] <= row[h] <= o["last_row"][t]
+        assert o["n_hits"][t] == (o["row_hit"][t] >= 0).sum()
+
+
+def test_f32_refit_reproduces_the_constructor_exactly():
+    """Two separate code paths of the oracle (search-and-fit vs refit of the
+    recorded hits) must give bit-identical binary32 results."""
+    b = synth.sector_workload(seed=3)
+    s = b.sector(0)
+    o = oracle.track_sector(s["y"], s["z"], s["row"], b.row_x, P, "f32")
+    r = oracle.refit(s["y"], s["z"], b.row_x, o["row_hit"], o["start_row"], P, "f32")
+    assert np.all(r["flags"] & 1)
+    assert np.array_equal(r["param"], o["param"]) and np.array_equal(r["cov"], o["cov"])
+    assert np.array_equal(r["x_ref"], o["x_ref"])
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_f32_parameters_agree_with_f64_refit(seed):
+    b = synth.sector_workload(seed=seed)
+    s = b.sector(0)
+    o = oracle.track_sector(s["y"], s["z"], s["row"], b.row_x, P, "f32")
+    r = oracle.refit(s["y"], s["z"], b.row_x, o["row_hit"], o["start_row"], P, "f64")
+    good = (r["flags"] & 1) != 0
+    assert good.mean() > 0.99
+    ok, d = within_tolerance(o["param"][good], r["param"][good], r["cov"][good])
+    assert ok.all(), d.max(0)
+    assert np.all(o["x_ref"][good] == r["x_ref"][good].astype(np.float32))
+
+
+def collect_pulls(seeds):
+    pulls = []
+    for seed in seeds:
+        b = synth.sector_workload(seed=seed, truth=True)
+        s = b.sector(0)
+        o = oracle.track_sector(s["y"], s["z"], s["row"], b.row_x, P, "f64")
+        lab, tr = s["label"], b.tracks[0]
+        for t in range(len(o["start"])):
+            if not o["flags"][t] & oracle.VALID:
+                continue
+            rh = o["row_hit"][t]
+            hits = rh[rh >= 0]
+            ls = lab[hits]
+            vals, cnt = np.unique(ls, return_counts=True)
+            L = vals[cnt.argmax()]
+            if L < 0 or cnt.max() < 0.9 * len(hits) or np.any(ls != L):
+                continue
+            h = rh[o["first_row"][t]]
+            truth = np.array([s["y_true"][h], s["z_true"][h], s["sinphi_true"][h], math.sinh(tr["eta"][L]),
+                              tr["q"][L] / tr["pt"][L]])
+            err = np.sqrt(o["cov"][t][[0, 2, 5, 9, 14]])
+            pulls.append((o["param"][t] - truth) / err)
+    return np.array(pulls)
+
+
+def test_transverse_pulls_are_standard_normal():
+    """Truth-matched tracklets (every hit from one track): (y, sin phi, q/pT)
+    pulls have mean ~0 and width ~1.  The longitudinal pulls are wider: the
+    decoupled filter transports z with path lengths computed from the
+    transverse state, whose early errors the z block does not know about; they
+    are bounded, not gated at 1."""
+    p = collect_pulls([11, 12, 13, 14])
+    assert len(p) > 800
+    mean, rms = p.mean(0), p.std(0)
+    for k in (0, 2, 4):
+        assert abs(mean[k]) < 0.15 and 0.85 < rms[k] < 1.15, (k, mean, rms)
+    for k in (1, 3):
+        assert abs(mean[k]) < 0.2 and rms[k] < 1.6, (k, mean, rms)
+
+
+def test_findable_tracks_are_found():
+    b = synth.sector_workload(seed=21, truth=True)
+    s = b.sector(0)
+    o = oracle.track_sector(s["y"], s["z"], s["row"], b.row_x, P, "f32")
+    lab = s["label"]
+    good = set()
+    for t in range(len(o["start"])):
+        if not o["flags"][t] & oracle.VALID:
+            continue
+        hits = o["row_hit"][t][o["row_hit"][t] >= 0]
+        vals, cnt = np.unique(lab[hits], return_counts=True)
+        if vals[cnt.argmax()] >= 0 and cnt.max() >= 0.9 * len(hits):
+            good.add(int(vals[cnt.argmax()]))
+    nh = np.bincount(lab[lab >= 0])
+    findable = set(np.flatnonzero(nh >= 30).tolist())
+    assert len(findable & good) >= 0.95 * len(findable)
+
+
+def test_precision_form_refit():
+    b = synth.sector_workload(seed=5)
+    s = b.sector(0)
+    base = oracle.track_sector(s["y"], s["z"], s["row"], b.row_x, P, "f32")
+    assert not np.any(base["flags"] & (oracle.SPD_FAIL | oracle.REFIT64))
+    p1 = oracle.Params(precision=1)
+    same = oracle.track_sector(s["y"], s["z"], s["row"], b.row_x, p1, "f32")
+    assert np.array_equal(same["param"], base["param"]) and np.array_equal(same["flags"], base["flags"])
+    p2 = oracle.Params(precision=2)  # refit every tracklet
+    allr = oracle.track_sector(s["y"], s["z"], s["row"], b.row_x, p2, "f32")
+    assert np.all(allr["flags"] & oracle.REFIT64)
+    assert np.array_equal(allr["row_hit"], base["row_hit"])
+    ref = oracle.refit(s["y"], s["z"], b.row_x, base["row_hit"], base["start_row"], P, "f64")
+    good = (ref["flags"] & 1) != 0
+    ok, d = within_tolerance(allr["param"][good], ref["param"][good], ref["cov"][good])
+    assert ok.all(), d.max(0)
+    m = oracle.refit_mixed(s["y"], s["z"], b.row_x, base["row_hit"], base["start_row"], P)
+    assert np.array_equal(m["param"], allr["param"]) and np.all(m["spd_ok"] == 1)
