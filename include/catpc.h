@@ -1,0 +1,190 @@
+/*
+ * catpc -- TPC sector tracking hot path on MI355X (gfx950): cellular-automaton
+ * neighbour finding over the pad rows and Kalman tracklet construction.
+ *
+ * Method: Rohr, Gorbunov, Lindenstruth, "GPU-accelerated track reconstruction
+ * in the ALICE High Level Trigger" (arXiv:1712.09430), Sec. 2 items 1-2
+ * (seeding with a cellular automaton, track following with a simplified
+ * Kalman filter), Fig. 2 c-d, Tab. 1 rows 1-2; problem statement per sector
+ * (Sec. 2: sectors are tracked independently), output size unknown in advance
+ * with a late fetch of what did not fit (Sec. 3.1), many events on one GPU at
+ * once (Sec. 3.2).
+ *
+ * Conventions for every call below
+ *  - Pointers named "device" are HIP device memory owned by the caller; the
+ *    library never frees them.  "host" pointers are read during the call only.
+ *  - Hits are given per sector, sectors concatenated: hits of sector s are the
+ *    global indices [hit_offset[s], hit_offset[s+1]), sorted by pad row inside
+ *    the sector.  Coordinates are sector-local (x along the pad-row normal),
+ *    float32, cm.  Every hit index the library returns is SECTOR-LOCAL
+ *    (0 .. n_s - 1), so a sector gives identical output alone or in a batch.
+ *  - All compute calls are asynchronous on the given stream (a hipStream_t
+ *    passed as void*; NULL = the null stream); results are valid after the
+ *    stream has been synchronised.  catpc_result() synchronises and reports
+ *    errors found on the device.
+ *  - Errors: a negative status; catpc_last_error() returns a thread-local
+ *    message describing the last failure.  Host-side validation failures leave
+ *    every output untouched.
+ *  - The hot calls allocate nothing: the workspace is allocated once by
+ *    catpc_create for the maximum sizes given there.
+ */
+#ifndef CATPC_H
+#define CATPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t catpc_status;
+#define CATPC_OK 0
+#define CATPC_E_INVALID (-1)  /* bad argument or invalid input hits */
+#define CATPC_E_CAPACITY (-2) /* more tracklets than output slots: fetch the rest */
+#define CATPC_E_HIP (-3)      /* a HIP runtime call failed */
+#define CATPC_E_STATE (-5)    /* call out of order (e.g. fetch before any track call) */
+
+/* tracklet flag bits */
+#define CATPC_FLAG_VALID 1       /* n_hits >= min_hits */
+#define CATPC_FLAG_STOP_SINPHI 2 /* a pass ended because |sin phi| reached 0.999 */
+#define CATPC_FLAG_STOP_ARC 4    /* a pass ended because |k * chord / 2| exceeded 0.2 */
+#define CATPC_FLAG_SPD_FAIL 8    /* binary32 covariance failed the positive-definiteness check */
+#define CATPC_FLAG_REFIT64 16    /* parameters come from the binary64-covariance refit */
+
+/* Method parameters (all float32 / int32).  Defaults in brackets. */
+typedef struct {
+  float bz;             /* solenoid field, T [0.5] */
+  float sigma_y;        /* cluster error in y, cm [0.1] */
+  float sigma_z;        /* cluster error in z, cm [0.1] */
+  float nf_win_y;       /* neighbour search half-window around the ray from the origin, y, cm [3] */
+  float nf_win_z;       /* same in z, cm [3] */
+  float nf_chi2_max;    /* cut on the 3-point chord residual dy^2 + dz^2, cm^2 [0.2] */
+  float tc_gate_nsigma; /* following gate in predicted standard deviations [3] */
+  int32_t tc_max_miss;  /* following ends after more consecutive empty rows than this [4] */
+  int32_t min_hits;     /* a tracklet is flagged valid with at least this many hits [10] */
+  int32_t precision;    /* 0: binary32 only; 1: refit SPD failures with a binary64 covariance;
+                           2: refit every tracklet that way (test hook) [0] */
+} catpc_params;
+
+/* Launch-shape tuning.  Results never depend on these values (tested). */
+typedef struct {
+  float bin_hits;        /* target hits per grid bin [2.0] */
+  int32_t nf_block;      /* threads per workgroup of the per-hit kernels [256] */
+  int32_t tc_block;      /* threads per workgroup of the tracklet kernel [256] */
+  int32_t tc_waves_per_cu; /* resident waves per CU of the persistent tracklet kernel [8] */
+  int32_t use_graph;     /* 1: replay the batched stage chain as a captured hipGraph [1] */
+} catpc_tuning;
+
+/* Input hits (device pointers). */
+typedef struct {
+  const float* y;                /* device [n_hits] */
+  const float* z;                /* device [n_hits] */
+  const int32_t* row;            /* device [n_hits], pad row 0 .. n_rows-1, sorted within each sector */
+  const int64_t* hit_offset;     /* device [n_sectors+1], hit_offset[0] == 0 */
+  const int64_t* hit_offset_host;/* host copy of hit_offset; required by catpc_track_plain, optional otherwise */
+  int32_t n_sectors;
+  int64_t n_hits;                /* == hit_offset[n_sectors] */
+} catpc_input;
+
+/* Outputs (device pointers, caller-owned). */
+typedef struct {
+  int32_t* link_up;          /* device [n_hits]: cleaned upward link (sector-local index) or -1 */
+  int32_t* link_dn;          /* device [n_hits]: cleaned downward link or -1 */
+  int32_t* nf_up;            /* device [n_hits] or NULL: raw neighbour-finder upward link */
+  int32_t* nf_dn;            /* device [n_hits] or NULL: raw neighbour-finder downward link */
+  int32_t* start_hit;        /* device [n_hits]: start hits, sector-local, ascending within each
+                                sector; sector s owns slots [tracklet_offset[s], tracklet_offset[s+1]) */
+  int64_t* tracklet_offset;  /* device [n_sectors+1]; tracklet slot j belongs to start_hit[j] */
+  int64_t tracklet_capacity; /* number of tracklet slots in the arrays below */
+  float* x_ref;              /* device [cap]: x of the fitted state (x of first_row) */
+  float* param;              /* device [cap][5]: y, z, sin phi, tan lambda, q/pT at x_ref */
+  float* cov;                /* device [cap][15]: packed lower triangle over the same order */
+  int32_t* row_hit;          /* device [cap][n_rows]: hit (sector-local) picked in each row, or -1 */
+  int32_t* start_row;        /* device [cap] */
+  int32_t* first_row;        /* device [cap] */
+  int32_t* last_row;         /* device [cap] */
+  int32_t* n_hits;           /* device [cap] */
+  int32_t* flags;            /* device [cap]: CATPC_FLAG_* */
+} catpc_output;
+
+typedef struct catpc_ctx catpc_ctx;
+
+/* Defaults of the method parameters and of the tuning. */
+void catpc_default_params(catpc_params* p);
+void catpc_default_tuning(catpc_tuning* t);
+
+/* Device workspace bytes catpc_create allocates for these maximum sizes. */
+size_t catpc_workspace_bytes(int32_t n_rows, int64_t max_hits, int32_t max_sectors);
+
+/* Create a tracker on the current HIP device.  row_x: host [n_rows], x of
+ * each pad row (cm, ascending); max_hits / max_sectors bound every later
+ * call.  Allocates the workspace once.  Returns CATPC_E_INVALID for bad sizes,
+ * CATPC_E_HIP if allocation fails. */
+catpc_status catpc_create(int32_t n_rows, const float* row_x, const catpc_params* params, int64_t max_hits,
+                          int32_t max_sectors, catpc_ctx** out);
+void catpc_destroy(catpc_ctx* ctx);
+
+catpc_status catpc_set_params(catpc_ctx* ctx, const catpc_params* params);
+catpc_status catpc_set_tuning(catpc_ctx* ctx, const catpc_tuning* tuning);
+catpc_status catpc_get_tuning(const catpc_ctx* ctx, catpc_tuning* tuning);
+
+/* Batched form: the whole hot path (row index and grid build, neighbour
+ * finding, link cleaning and start hits, tracklet construction, optional
+ * precision refit) over all sectors of the input in a fixed chain of
+ * launches, independent of the number of sectors; replayed as a hipGraph
+ * when tuning.use_graph is set and the arguments match the captured chain.
+ * Tracklet slots [0, tracklet_capacity) are written; see catpc_result. */
+catpc_status catpc_track_batch(catpc_ctx* ctx, const catpc_input* in, const catpc_output* out, void* stream);
+
+/* Plain form: the same stages launched sector by sector (input.hit_offset_host
+ * required).  Output identical to catpc_track_batch. */
+catpc_status catpc_track_plain(catpc_ctx* ctx, const catpc_input* in, const catpc_output* out, void* stream);
+
+/* Synchronise the stream and report: CATPC_E_INVALID if the device found hits
+ * that are not row-sorted or a row out of range (outputs undefined), else
+ * CATPC_E_CAPACITY if the last track call found more tracklets than its
+ * output slots, else CATPC_OK.  *n_tracklets (may be NULL) receives the total
+ * number of tracklets of the last track call. */
+catpc_status catpc_result(catpc_ctx* ctx, void* stream, int64_t* n_tracklets);
+
+/* Late fetch (Sec. 3.1: queue an estimated output buffer, fetch the rest
+ * afterwards): construct tracklet slots [first, first + out->tracklet_capacity)
+ * of the last track call into out (slot first goes to index 0).  Only the
+ * tracklet arrays of out are used.  The input must be the same, unchanged,
+ * and no other track call may have run on ctx since. */
+catpc_status catpc_fetch_tracklets(catpc_ctx* ctx, const catpc_input* in, int64_t first, const catpc_output* out,
+                                   void* stream);
+
+/* Number of stages reported by catpc_stage_times, in chain order:
+ * 0 row index + input validation, 1 row grids, 2 neighbour finding,
+ * 3 link cleaning + start-hit bits, 4 start-count scan, 5 start-list
+ * compaction + per-sector tracklet offsets, 6 tracklet construction,
+ * 7 precision refit (0 when precision == 0). */
+#define CATPC_N_STAGES 8
+
+/* Measurement: run the batched chain once without the graph, with a HIP event
+ * before each stage, on `stream`; synchronise and write the elapsed
+ * milliseconds of each stage to ms[CATPC_N_STAGES] (host).  Outputs as
+ * catpc_track_batch. */
+catpc_status catpc_stage_times(catpc_ctx* ctx, const catpc_input* in, const catpc_output* out, void* stream,
+                               float* ms);
+
+/* Measurement: the tracklet kernel's own count of method steps in the last
+ * track call (accumulated over fetches): counts[0] helix transports,
+ * [1] Kalman updates, [2] cluster candidates inside a following gate,
+ * [3] row searches (host int64[4]).  Synchronises the stream. */
+catpc_status catpc_work_counts(catpc_ctx* ctx, void* stream, int64_t* counts);
+
+/* Numerics probe: out[i] = a[i] OP b[i] on the device in binary32 for
+ * op 0 '+', 1 '-', 2 '*', 3 '/', 4 sqrt(a[i]); device pointers, n elements.
+ * Used to check that the device rounds like the host. */
+catpc_status catpc_fp32_probe(int32_t op, const float* a, const float* b, float* out, int64_t n, void* stream);
+
+/* Thread-local text of the last error. */
+const char* catpc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

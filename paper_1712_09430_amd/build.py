@@ -1,0 +1,35 @@
+"""Compile the HIP library (gfx950) into paper_1712_09430_amd/libcatpc.so.
+
+hipcc flags: -ffp-contract=off and no fast-math keep every float operation a
+separately rounded IEEE operation (the filter's operation order is part of its
+definition); packed FP32 instructions are disabled.
+"""
+import os
+import subprocess
+import tempfile
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libcatpc.so")
+SOURCES = ["kernels.hip", "api.hip"]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result"]
+
+
+def build(force: bool = True) -> str:
+    if not force and os.path.exists(LIB):
+        return LIB
+    with tempfile.TemporaryDirectory() as tmp:
+        objs = []
+        for src in SOURCES:
+            o = os.path.join(tmp, src + ".o")
+            subprocess.run([HIPCC, *FLAGS, "-c", os.path.join(HERE, "csrc", src), "-o", o], check=True)
+            objs.append(o)
+        out = LIB + ".tmp"
+        subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", out], check=True)
+        os.replace(out, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build())

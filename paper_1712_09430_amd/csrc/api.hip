@@ -1,0 +1,552 @@
+// Host runtime of catpc: context and workspace, validation, the batched and
+// plain stage chains, hipGraph replay of the batched chain, late fetch.
+// Public C ABI: include/catpc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/catpc.h"
+#include "internal.h"
+
+using namespace catpc;
+
+namespace {
+
+thread_local std::string g_err;
+
+catpc_status fail(catpc_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+catpc_status hip_fail(hipError_t e, const char* what) {
+  return fail(CATPC_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                  \
+  do {                                                 \
+    hipError_t _e = (expr);                            \
+    if (_e != hipSuccess) return hip_fail(_e, #expr);  \
+  } while (0)
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t row_first, grid_f, grid_n, bins, sorted, raw_up, raw_dn, mask, blk_cnt, blk_off, start_glob, counters;
+  size_t total;
+};
+
+Layout plan(int32_t R, int64_t H, int32_t S) {
+  Layout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t p = o; o += align_up(bytes); return p; };
+  const size_t nblk = (size_t)(H / kHitsPerBlock) + 8;
+  L.row_first = take(sizeof(int32_t) * (size_t)S * (R + 1));
+  L.grid_f = take(sizeof(float4) * (size_t)S * R);
+  L.grid_n = take(sizeof(int2) * (size_t)S * R);
+  L.bins = take(sizeof(int32_t) * (2 * (size_t)H + 2 * (size_t)S * R + 8));
+  L.sorted = take(sizeof(SortedHit) * (size_t)(H + 1));
+  L.raw_up = take(sizeof(int32_t) * (size_t)(H + 1));
+  L.raw_dn = take(sizeof(int32_t) * (size_t)(H + 1));
+  L.mask = take(sizeof(uint64_t) * (nblk * (kHitsPerBlock / 64) + 8));
+  L.blk_cnt = take(sizeof(int32_t) * (nblk + 8));
+  L.blk_off = take(sizeof(int64_t) * (nblk + 8));
+  L.start_glob = take(sizeof(int32_t) * (size_t)(H + 1));
+  L.counters = take(sizeof(unsigned long long) * 8);
+  L.total = o;
+  return L;
+}
+
+// Arguments of the last captured batched chain; replay only if identical.
+struct GraphKey {
+  catpc_input in;
+  catpc_output out;
+  catpc_params params;
+  catpc_tuning tuning;
+  bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
+};
+
+}  // namespace
+
+struct catpc_ctx {
+  int device = 0;
+  int n_cu = 256;
+  int32_t n_rows = 0;
+  int64_t max_hits = 0;
+  int32_t max_sectors = 0;
+  float* row_x = nullptr;  // device [n_rows]
+  catpc_params params{};
+  catpc_tuning tuning{};
+  Consts consts{};
+  void* ws_mem = nullptr;
+  Workspace ws{};
+  unsigned long long* host_counters = nullptr;  // pinned [8]
+  int64_t* host_total = nullptr;                 // pinned [1]
+  // last track call
+  bool have_last = false;
+  catpc_input last_in{};
+  catpc_output last_out{};
+  // graph cache
+  bool have_graph = false;
+  GraphKey key{};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t capture_stream = nullptr;  // the batched chain is captured here, replayed on the caller's stream
+};
+
+namespace {
+
+Consts make_consts(const catpc_params& p) {
+  Consts c;
+  c.kb = -0.00299792458f * p.bz;
+  c.sy2 = p.sigma_y * p.sigma_y;
+  c.sz2 = p.sigma_z * p.sigma_z;
+  c.wy = p.nf_win_y;
+  c.wz = p.nf_win_z;
+  c.chi2 = p.nf_chi2_max;
+  c.nsig = p.tc_gate_nsigma;
+  c.max_miss = p.tc_max_miss;
+  c.min_hits = p.min_hits;
+  c.precision = p.precision;
+  c.sy2d = (double)p.sigma_y * (double)p.sigma_y;
+  c.sz2d = (double)p.sigma_z * (double)p.sigma_z;
+  return c;
+}
+
+catpc_status check_params(const catpc_params* p) {
+  if (!p) return fail(CATPC_E_INVALID, "params is NULL");
+  if (!(p->sigma_y > 0) || !(p->sigma_z > 0)) return fail(CATPC_E_INVALID, "cluster errors must be > 0");
+  if (!(p->nf_win_y >= 0) || !(p->nf_win_z >= 0) || !(p->nf_chi2_max >= 0) || !(p->tc_gate_nsigma >= 0))
+    return fail(CATPC_E_INVALID, "windows and cuts must be >= 0");
+  if (p->tc_max_miss < 0 || p->min_hits < 0) return fail(CATPC_E_INVALID, "tc_max_miss and min_hits must be >= 0");
+  if (p->precision < 0 || p->precision > 2) return fail(CATPC_E_INVALID, "precision must be 0, 1 or 2");
+  return CATPC_OK;
+}
+
+catpc_status check_io(const catpc_ctx* ctx, const catpc_input* in, const catpc_output* out, bool need_host_off) {
+  if (!ctx) return fail(CATPC_E_INVALID, "ctx is NULL");
+  if (!in || !out) return fail(CATPC_E_INVALID, "input or output is NULL");
+  if (in->n_sectors < 0 || in->n_sectors > ctx->max_sectors)
+    return fail(CATPC_E_INVALID, "n_sectors out of [0, max_sectors]");
+  if (in->n_hits < 0 || in->n_hits > ctx->max_hits) return fail(CATPC_E_INVALID, "n_hits out of [0, max_hits]");
+  if (in->n_sectors == 0) return CATPC_OK;
+  if (!in->hit_offset) return fail(CATPC_E_INVALID, "hit_offset is NULL");
+  if (in->n_hits > 0 && (!in->y || !in->z || !in->row)) return fail(CATPC_E_INVALID, "hit arrays are NULL");
+  if (!out->tracklet_offset) return fail(CATPC_E_INVALID, "tracklet_offset is required");
+  if (in->n_hits > 0 && (!out->link_up || !out->link_dn || !out->start_hit))
+    return fail(CATPC_E_INVALID, "link_up, link_dn and start_hit are required");
+  if (out->tracklet_capacity < 0) return fail(CATPC_E_INVALID, "tracklet_capacity < 0");
+  if (out->tracklet_capacity > 0 &&
+      (!out->x_ref || !out->param || !out->cov || !out->row_hit || !out->start_row || !out->first_row ||
+       !out->last_row || !out->n_hits || !out->flags))
+    return fail(CATPC_E_INVALID, "tracklet arrays are NULL");
+  if (need_host_off) {
+    const int64_t* h = in->hit_offset_host;
+    if (!h) return fail(CATPC_E_INVALID, "hit_offset_host is required");
+    if (h[0] != 0 || h[in->n_sectors] != in->n_hits) return fail(CATPC_E_INVALID, "hit_offset_host inconsistent");
+    for (int32_t s = 0; s < in->n_sectors; ++s)
+      if (h[s + 1] < h[s]) return fail(CATPC_E_INVALID, "hit_offset_host not monotone");
+  } else if (in->hit_offset_host) {
+    const int64_t* h = in->hit_offset_host;
+    if (h[0] != 0 || h[in->n_sectors] != in->n_hits) return fail(CATPC_E_INVALID, "hit_offset_host inconsistent");
+  }
+  return CATPC_OK;
+}
+
+Inputs inputs_of(const catpc_input* in) {
+  Inputs I;
+  I.y = in->y;
+  I.z = in->z;
+  I.row = in->row;
+  I.hit_offset = in->hit_offset;
+  return I;
+}
+
+TrackletOut tracklets_of(const catpc_output* out) {
+  TrackletOut T;
+  T.x_ref = out->x_ref;
+  T.param = out->param;
+  T.cov = out->cov;
+  T.row_hit = out->row_hit;
+  T.start_row = out->start_row;
+  T.first_row = out->first_row;
+  T.last_row = out->last_row;
+  T.n_hits = out->n_hits;
+  T.flags = out->flags;
+  return T;
+}
+
+// Persistent grid of the tracklet kernel; `max_tracklets` (if >= 0) bounds
+// the useful number of waves (a seed has at least three hits).
+int tc_grid(const catpc_ctx* ctx, int64_t max_tracklets = -1) {
+  int64_t waves = (int64_t)ctx->n_cu * (ctx->tuning.tc_waves_per_cu > 0 ? ctx->tuning.tc_waves_per_cu : 8);
+  if (max_tracklets >= 0) waves = std::min<int64_t>(waves, std::max<int64_t>(1, (max_tracklets + 63) / 64));
+  const int64_t wpb = ctx->tuning.tc_block / 64;
+  return (int)((waves + wpb - 1) / wpb);
+}
+
+// The stage chain for sectors [s0, s1) with hits [h0, h1).  With `ev`
+// (CATPC_N_STAGES + 1 events) an event is recorded before each stage and after
+// the last one.
+catpc_status enqueue_span(catpc_ctx* ctx, const catpc_input* in, const catpc_output* out, Span sp, hipStream_t st,
+                          hipEvent_t* ev = nullptr) {
+  const Inputs I = inputs_of(in);
+  const Workspace& ws = ctx->ws;
+  int32_t* up = out->nf_up ? out->nf_up : ws.raw_up;
+  int32_t* dn = out->nf_dn ? out->nf_dn : ws.raw_dn;
+  const int nb = ctx->tuning.nf_block;
+  auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev[k], st) : hipSuccess; };
+  HIP_TRY(mark(0));
+  HIP_TRY(launch_row_index(I, sp, ctx->n_rows, ws, nb, st));
+  HIP_TRY(mark(1));
+  HIP_TRY(launch_grid(I, sp, ctx->n_rows, ctx->tuning.bin_hits, ws, st));
+  HIP_TRY(mark(2));
+  HIP_TRY(launch_neighbours(I, sp, ctx->n_rows, ctx->row_x, ctx->consts, ws, up, dn, nb, st));
+  HIP_TRY(mark(3));
+  HIP_TRY(launch_clean_start(I, sp, up, dn, out->link_up, out->link_dn, ws, st));
+  HIP_TRY(mark(4));
+  HIP_TRY(launch_scan(sp, out->tracklet_offset, ws, st));
+  HIP_TRY(mark(5));
+  HIP_TRY(launch_compact(I, sp, out->tracklet_offset, out->start_hit, ws, st));
+  HIP_TRY(mark(6));
+  if (out->tracklet_capacity > 0) {
+    HIP_TRY(launch_tracklets(I, sp, ctx->n_rows, ctx->row_x, ctx->consts, ws, out->link_up, out->tracklet_offset, 0,
+                             out->tracklet_capacity, tracklets_of(out), tc_grid(ctx, (sp.h1 - sp.h0) / 3 + 1),
+                             ctx->tuning.tc_block, st));
+  }
+  HIP_TRY(mark(7));
+  return CATPC_OK;
+}
+
+catpc_status enqueue_refit(catpc_ctx* ctx, const catpc_input* in, const catpc_output* out, Span sp, int64_t first,
+                           hipStream_t st) {
+  if (ctx->params.precision == 0 || out->tracklet_capacity == 0) return CATPC_OK;
+  HIP_TRY(launch_refit64(inputs_of(in), sp, ctx->n_rows, ctx->row_x, ctx->consts, ctx->ws, out->tracklet_offset,
+                         first, out->tracklet_capacity, tracklets_of(out), ctx->n_cu * 4, st));
+  return CATPC_OK;
+}
+
+catpc_status enqueue_batch(catpc_ctx* ctx, const catpc_input* in, const catpc_output* out, hipStream_t st) {
+  HIP_TRY(launch_reset(ctx->ws.counters, 8, st));
+  if (in->n_sectors == 0) return CATPC_OK;
+  Span sp{0, in->n_sectors, 0, in->n_hits};
+  catpc_status rc = enqueue_span(ctx, in, out, sp, st);
+  if (rc) return rc;
+  return enqueue_refit(ctx, in, out, sp, 0, st);
+}
+
+void drop_graph(catpc_ctx* ctx) {
+  if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  ctx->exec = nullptr;
+  ctx->graph = nullptr;
+  ctx->have_graph = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+void catpc_default_params(catpc_params* p) {
+  if (!p) return;
+  p->bz = 0.5f;
+  p->sigma_y = 0.1f;
+  p->sigma_z = 0.1f;
+  p->nf_win_y = 3.0f;
+  p->nf_win_z = 3.0f;
+  p->nf_chi2_max = 0.2f;
+  p->tc_gate_nsigma = 3.0f;
+  p->tc_max_miss = 4;
+  p->min_hits = 10;
+  p->precision = 0;
+}
+
+void catpc_default_tuning(catpc_tuning* t) {
+  if (!t) return;
+  t->bin_hits = 2.0f;
+  t->nf_block = 256;
+  t->tc_block = 256;
+  t->tc_waves_per_cu = 8;
+  t->use_graph = 1;
+}
+
+size_t catpc_workspace_bytes(int32_t n_rows, int64_t max_hits, int32_t max_sectors) {
+  if (n_rows < 3 || max_hits < 0 || max_sectors < 0) return 0;
+  return plan(n_rows, max_hits, max_sectors).total + sizeof(float) * (size_t)n_rows;
+}
+
+const char* catpc_last_error(void) { return g_err.c_str(); }
+
+catpc_status catpc_create(int32_t n_rows, const float* row_x, const catpc_params* params, int64_t max_hits,
+                          int32_t max_sectors, catpc_ctx** out) {
+  if (!out) return fail(CATPC_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (n_rows < 3 || !row_x) return fail(CATPC_E_INVALID, "need n_rows >= 3 and row_x");
+  for (int32_t r = 0; r < n_rows; ++r)
+    if (!(row_x[r] > 0.0f) || (r > 0 && !(row_x[r] > row_x[r - 1])))
+      return fail(CATPC_E_INVALID, "row_x must be positive and strictly ascending");
+  if (max_hits < 0 || max_hits >= (int64_t)1 << 31) return fail(CATPC_E_INVALID, "max_hits out of [0, 2^31)");
+  if (max_sectors < 0 || (int64_t)max_sectors * n_rows >= (int64_t)1 << 31)
+    return fail(CATPC_E_INVALID, "max_sectors out of range");
+  catpc_status rc = check_params(params);
+  if (rc) return rc;
+  catpc_ctx* ctx = new (std::nothrow) catpc_ctx();
+  if (!ctx) return fail(CATPC_E_HIP, "host allocation failed");
+  ctx->n_rows = n_rows;
+  ctx->max_hits = max_hits;
+  ctx->max_sectors = max_sectors;
+  ctx->params = *params;
+  ctx->consts = make_consts(*params);
+  catpc_default_tuning(&ctx->tuning);
+  hipError_t e = hipGetDevice(&ctx->device);
+  if (e == hipSuccess) {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess && ncu > 0)
+      ctx->n_cu = ncu;
+    const Layout L = plan(n_rows, max_hits, max_sectors);
+    e = hipMalloc(&ctx->ws_mem, L.total);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->row_x, sizeof(float) * (size_t)n_rows);
+    if (e == hipSuccess) e = hipMemcpy(ctx->row_x, row_x, sizeof(float) * (size_t)n_rows, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->host_counters, sizeof(unsigned long long) * 8, 0);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->host_total, sizeof(int64_t), 0);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+      char* b = (char*)ctx->ws_mem;
+      Workspace& w = ctx->ws;
+      w.row_first = (int32_t*)(b + L.row_first);
+      w.grid_f = (float4*)(b + L.grid_f);
+      w.grid_n = (int2*)(b + L.grid_n);
+      w.bins = (int32_t*)(b + L.bins);
+      w.sorted = (SortedHit*)(b + L.sorted);
+      w.raw_up = (int32_t*)(b + L.raw_up);
+      w.raw_dn = (int32_t*)(b + L.raw_dn);
+      w.start_mask = (uint64_t*)(b + L.mask);
+      w.blk_cnt = (int32_t*)(b + L.blk_cnt);
+      w.blk_off = (int64_t*)(b + L.blk_off);
+      w.start_glob = (int32_t*)(b + L.start_glob);
+      w.counters = (unsigned long long*)(b + L.counters);
+      e = hipMemset(w.counters, 0, sizeof(unsigned long long) * 8);
+    }
+  }
+  if (e != hipSuccess) {
+    catpc_destroy(ctx);
+    return hip_fail(e, "catpc_create");
+  }
+  *out = ctx;
+  return CATPC_OK;
+}
+
+void catpc_destroy(catpc_ctx* ctx) {
+  if (!ctx) return;
+  drop_graph(ctx);
+  if (ctx->ws_mem) (void)hipFree(ctx->ws_mem);
+  if (ctx->row_x) (void)hipFree(ctx->row_x);
+  if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
+  if (ctx->host_total) (void)hipHostFree(ctx->host_total);
+  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+  delete ctx;
+}
+
+catpc_status catpc_set_params(catpc_ctx* ctx, const catpc_params* params) {
+  if (!ctx) return fail(CATPC_E_INVALID, "ctx is NULL");
+  catpc_status rc = check_params(params);
+  if (rc) return rc;
+  ctx->params = *params;
+  ctx->consts = make_consts(*params);
+  return CATPC_OK;
+}
+
+catpc_status catpc_set_tuning(catpc_ctx* ctx, const catpc_tuning* t) {
+  if (!ctx || !t) return fail(CATPC_E_INVALID, "ctx or tuning is NULL");
+  if (!(t->bin_hits >= 0.25f && t->bin_hits <= 64.0f)) return fail(CATPC_E_INVALID, "bin_hits out of [0.25, 64]");
+  if (t->nf_block < 64 || t->nf_block > 256 || t->nf_block % 64)
+    return fail(CATPC_E_INVALID, "nf_block must be a multiple of 64 in [64, 256]");
+  if (t->tc_block < 64 || t->tc_block > 256 || t->tc_block % 64)
+    return fail(CATPC_E_INVALID, "tc_block must be a multiple of 64 in [64, 256]");
+  if (t->tc_waves_per_cu < 1 || t->tc_waves_per_cu > 32) return fail(CATPC_E_INVALID, "tc_waves_per_cu out of [1, 32]");
+  ctx->tuning = *t;
+  return CATPC_OK;
+}
+
+catpc_status catpc_get_tuning(const catpc_ctx* ctx, catpc_tuning* t) {
+  if (!ctx || !t) return fail(CATPC_E_INVALID, "ctx or tuning is NULL");
+  *t = ctx->tuning;
+  return CATPC_OK;
+}
+
+catpc_status catpc_track_batch(catpc_ctx* ctx, const catpc_input* in, const catpc_output* out, void* stream) {
+  catpc_status rc = check_io(ctx, in, out, false);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  ctx->have_last = false;
+  if (ctx->tuning.use_graph && in->n_sectors > 0) {
+    GraphKey k;
+    std::memset(&k, 0, sizeof k);
+    k.in.y = in->y;
+    k.in.z = in->z;
+    k.in.row = in->row;
+    k.in.hit_offset = in->hit_offset;
+    k.in.n_sectors = in->n_sectors;
+    k.in.n_hits = in->n_hits;
+    k.out = *out;
+    k.params = ctx->params;
+    k.tuning = ctx->tuning;
+    if (!ctx->have_graph || !(k == ctx->key)) {
+      drop_graph(ctx);
+      hipStream_t cs = ctx->capture_stream;
+      HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      rc = enqueue_batch(ctx, in, out, cs);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(cs, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&ctx->exec, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "hipGraphInstantiate");
+      }
+      ctx->graph = g;
+      ctx->key = k;
+      ctx->have_graph = true;
+    }
+    HIP_TRY(hipGraphLaunch(ctx->exec, st));
+  } else {
+    rc = enqueue_batch(ctx, in, out, st);
+    if (rc) return rc;
+  }
+  ctx->last_in = *in;
+  ctx->last_in.hit_offset_host = nullptr;
+  ctx->last_out = *out;
+  ctx->have_last = true;
+  return CATPC_OK;
+}
+
+catpc_status catpc_track_plain(catpc_ctx* ctx, const catpc_input* in, const catpc_output* out, void* stream) {
+  catpc_status rc = check_io(ctx, in, out, true);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  ctx->have_last = false;
+  HIP_TRY(launch_reset(ctx->ws.counters, 8, st));
+  const int64_t* h = in->hit_offset_host;
+  for (int32_t s = 0; s < in->n_sectors; ++s) {
+    Span sp{s, s + 1, h[s], h[s + 1]};
+    rc = enqueue_span(ctx, in, out, sp, st);
+    if (rc) return rc;
+  }
+  if (in->n_sectors > 0) {
+    rc = enqueue_refit(ctx, in, out, Span{0, in->n_sectors, 0, in->n_hits}, 0, st);
+    if (rc) return rc;
+  }
+  ctx->last_in = *in;
+  ctx->last_in.hit_offset_host = nullptr;
+  ctx->last_out = *out;
+  ctx->have_last = true;
+  return CATPC_OK;
+}
+
+catpc_status catpc_result(catpc_ctx* ctx, void* stream, int64_t* n_tracklets) {
+  if (!ctx) return fail(CATPC_E_INVALID, "ctx is NULL");
+  if (!ctx->have_last) return fail(CATPC_E_STATE, "no completed track call");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipMemcpyAsync(ctx->host_counters, ctx->ws.counters, sizeof(unsigned long long) * 8,
+                         hipMemcpyDeviceToHost, st));
+  int64_t total = 0;
+  if (ctx->last_in.n_sectors > 0) {
+    HIP_TRY(hipMemcpyAsync(ctx->host_total, ctx->last_out.tracklet_offset + ctx->last_in.n_sectors, sizeof(int64_t),
+                           hipMemcpyDeviceToHost, st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  if (ctx->last_in.n_sectors > 0) total = *ctx->host_total;
+  if (n_tracklets) *n_tracklets = total;
+  if (ctx->host_counters[1] & 1ull) return fail(CATPC_E_INVALID, "hits not sorted by row, or a row out of range");
+  if (total > ctx->last_out.tracklet_capacity)
+    return fail(CATPC_E_CAPACITY, "more tracklets (" + std::to_string(total) + ") than output slots (" +
+                                      std::to_string(ctx->last_out.tracklet_capacity) + ")");
+  return CATPC_OK;
+}
+
+catpc_status catpc_fetch_tracklets(catpc_ctx* ctx, const catpc_input* in, int64_t first, const catpc_output* out,
+                                   void* stream) {
+  if (!ctx || !in || !out) return fail(CATPC_E_INVALID, "NULL argument");
+  if (!ctx->have_last) return fail(CATPC_E_STATE, "no track call to fetch from");
+  if (in->n_sectors != ctx->last_in.n_sectors || in->n_hits != ctx->last_in.n_hits || in->y != ctx->last_in.y ||
+      in->z != ctx->last_in.z || in->row != ctx->last_in.row || in->hit_offset != ctx->last_in.hit_offset)
+    return fail(CATPC_E_STATE, "fetch needs the input of the last track call");
+  if (first < 0) return fail(CATPC_E_INVALID, "first < 0");
+  if (out->tracklet_capacity < 0) return fail(CATPC_E_INVALID, "tracklet_capacity < 0");
+  if (out->tracklet_capacity == 0 || in->n_sectors == 0) return CATPC_OK;
+  if (!out->x_ref || !out->param || !out->cov || !out->row_hit || !out->start_row || !out->first_row ||
+      !out->last_row || !out->n_hits || !out->flags)
+    return fail(CATPC_E_INVALID, "tracklet arrays are NULL");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const Span sp{0, in->n_sectors, 0, in->n_hits};
+  const Inputs I = inputs_of(in);
+  catpc_output o = *out;
+  o.tracklet_offset = ctx->last_out.tracklet_offset;
+  HIP_TRY(launch_reset(ctx->ws.counters, 1, st));
+  HIP_TRY(launch_tracklets(I, sp, ctx->n_rows, ctx->row_x, ctx->consts, ctx->ws, ctx->last_out.link_up,
+                           o.tracklet_offset, first, o.tracklet_capacity, tracklets_of(&o), tc_grid(ctx),
+                           ctx->tuning.tc_block, st));
+  return enqueue_refit(ctx, in, &o, sp, first, st);
+}
+
+catpc_status catpc_stage_times(catpc_ctx* ctx, const catpc_input* in, const catpc_output* out, void* stream,
+                               float* ms) {
+  catpc_status rc = check_io(ctx, in, out, false);
+  if (rc) return rc;
+  if (!ms) return fail(CATPC_E_INVALID, "ms is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  ctx->have_last = false;
+  hipEvent_t ev[CATPC_N_STAGES + 1] = {};
+  for (int k = 0; k <= CATPC_N_STAGES; ++k) HIP_TRY(hipEventCreate(&ev[k]));
+  HIP_TRY(launch_reset(ctx->ws.counters, 8, st));
+  const Span sp{0, in->n_sectors, 0, in->n_hits};
+  if (in->n_sectors > 0) {
+    rc = enqueue_span(ctx, in, out, sp, st, ev);
+    if (!rc) rc = enqueue_refit(ctx, in, out, sp, 0, st);
+  } else {
+    for (int k = 0; k < CATPC_N_STAGES; ++k) HIP_TRY(hipEventRecord(ev[k], st));
+  }
+  if (!rc) {
+    HIP_TRY(hipEventRecord(ev[CATPC_N_STAGES], st));
+    HIP_TRY(hipEventSynchronize(ev[CATPC_N_STAGES]));
+    for (int k = 0; k < CATPC_N_STAGES; ++k) HIP_TRY(hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]));
+    ctx->last_in = *in;
+    ctx->last_in.hit_offset_host = nullptr;
+    ctx->last_out = *out;
+    ctx->have_last = true;
+  }
+  for (int k = 0; k <= CATPC_N_STAGES; ++k) (void)hipEventDestroy(ev[k]);
+  return rc;
+}
+
+catpc_status catpc_work_counts(catpc_ctx* ctx, void* stream, int64_t* counts) {
+  if (!ctx || !counts) return fail(CATPC_E_INVALID, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipMemcpyAsync(ctx->host_counters, ctx->ws.counters, sizeof(unsigned long long) * 8,
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int k = 0; k < 4; ++k) counts[k] = (int64_t)ctx->host_counters[2 + k];
+  return CATPC_OK;
+}
+
+catpc_status catpc_fp32_probe(int32_t op, const float* a, const float* b, float* out, int64_t n, void* stream) {
+  if (op < 0 || op > 4 || n < 0 || (n > 0 && (!a || !b || !out))) return fail(CATPC_E_INVALID, "bad probe arguments");
+  HIP_TRY(launch_fp32_probe(op, a, b, out, n, (hipStream_t)stream));
+  return CATPC_OK;
+}
+
+}  // extern "C"

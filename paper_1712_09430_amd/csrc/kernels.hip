@@ -1,0 +1,880 @@
+// HIP kernels (gfx950, wave64) of the sector-tracking hot path.
+//
+// Paper: arXiv:1712.09430, Sec. 2 item 1 (cellular-automaton seeding: links
+// between hits of adjacent pad rows, seeds of at least three hits oriented
+// along x) and item 2 (track following: fit the seed, extrapolate row by row,
+// take the closest cluster per row, refine with a simplified Kalman filter in
+// a constant field); Fig. 2 c-d; Tab. 1 rows 1-2.
+//
+// Floating point: compiled with -ffp-contract=off and without fast-math, so
+// every float operation below is one IEEE binary32 operation rounded to
+// nearest, in the order written (division and square root correctly
+// rounded).  The operation order of the filter is part of the method's
+// definition here: a different order would change results in the last bit and
+// with them the hits that the gates accept.
+//
+// Layout and stage chain, for the sectors [s0, s1) of one call:
+//   row index   per (sector, row): first hit of each row (binary search);
+//               per hit: row range and order validation
+//   grid        one wave per (sector, row): bounding box, bins, counting
+//               sort of the row's hits into bin order (SortedHit)
+//   neighbours  one thread per hit: best (up, down) pair in rows r+-1
+//   clean/start one thread per hit: mutual links, start-hit bit (ballot)
+//   scan        one workgroup: exclusive scan of per-block start counts
+//   compact     one thread per hit: start list, per-sector tracklet offsets
+//   tracklets   persistent, one lane per tracklet: seed chain, outward
+//               following, back-transport, inward following
+//   refit64     one lane per tracklet needing it: binary64-covariance refit
+#include <float.h>
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace catpc {
+namespace {
+
+__device__ __forceinline__ int sector_of(const int64_t* off, int s0, int s1, int64_t i) {
+  // largest s in [s0, s1) with off[s] <= i  (off[s0] <= i < off[s1])
+  int lo = s0, hi = s1;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Bin of a coordinate: monotone non-decreasing in v, clamped to [0, n-1].
+__device__ __forceinline__ int bin_of(float v, float vmin, float inv, int n) {
+  float f = (v - vmin) * inv;
+  f = fminf(fmaxf(f, 0.0f), (float)(n - 1));
+  return (int)f;
+}
+
+struct RowGrid {
+  float ymin, zmin, iby, ibz;
+  int ny, nz;
+  const int32_t* bins;
+  const SortedHit* hits;
+};
+
+__device__ __forceinline__ RowGrid row_grid(const Inputs& in, const Workspace& ws, int R, int s, int r) {
+  RowGrid G;
+  const int64_t gid = (int64_t)s * R + r;
+  const int2 nn = ws.grid_n[gid];
+  G.ny = nn.x;
+  G.nz = nn.y;
+  if (G.ny > 0) {
+    const float4 f = ws.grid_f[gid];
+    G.ymin = f.x; G.zmin = f.y; G.iby = f.z; G.ibz = f.w;
+    const int64_t g = in.hit_offset[s] + ws.row_first[(int64_t)s * (R + 1) + r];
+    G.bins = ws.bins + 2 * g + 2 * gid;
+    G.hits = ws.sorted + g;
+  }
+  return G;
+}
+
+// ------------------------------------------------------------------- reset
+__global__ void k_reset(unsigned long long* c, int n) {
+  if ((int)threadIdx.x < n) c[threadIdx.x] = 0ull;
+}
+
+// --------------------------------------------------------------- row index
+__global__ __launch_bounds__(256) void k_row_index(Inputs in, Span sp, int R, int32_t* row_first,
+                                                   unsigned long long* counters, int64_t n_items) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n_items) {
+    const int s = sp.s0 + (int)(g / (R + 1));
+    const int r = (int)(g % (R + 1));
+    const int64_t a = in.hit_offset[s], b = in.hit_offset[s + 1];
+    int64_t lo = a, hi = b;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (in.row[mid] < r) lo = mid + 1; else hi = mid;
+    }
+    row_first[(int64_t)s * (R + 1) + r] = (int32_t)((r == R ? b : lo) - a);
+  } else {
+    const int64_t i = sp.h0 + (g - n_items);
+    if (i < sp.h1) {
+      const int s = sector_of(in.hit_offset, sp.s0, sp.s1, i);
+      const int32_t r = in.row[i];
+      bool ok = r >= 0 && r < R;
+      if (i > in.hit_offset[s]) ok = ok && in.row[i - 1] <= r;
+      if (!ok) atomicOr(&counters[1], 1ull);
+    }
+  }
+}
+
+// -------------------------------------------------------------------- grid
+__device__ __forceinline__ float wave_min(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
+__global__ __launch_bounds__(64) void k_grid(Inputs in, Span sp, int R, float bin_hits, Workspace ws) {
+  __shared__ int cnt[kMaxBinsPerRow];
+  const int item = blockIdx.x;
+  const int s = sp.s0 + item / R;
+  const int r = item % R;
+  const int lane = threadIdx.x;
+  const int64_t gid = (int64_t)s * R + r;
+  const int64_t a = in.hit_offset[s];
+  const int32_t f0 = ws.row_first[(int64_t)s * (R + 1) + r];
+  const int32_t f1 = ws.row_first[(int64_t)s * (R + 1) + r + 1];
+  const int n = f1 - f0;
+  if (n <= 0) {
+    if (lane == 0) ws.grid_n[gid] = make_int2(0, 0);
+    return;
+  }
+  const int64_t g = a + f0;
+  float ylo = FLT_MAX, yhi = -FLT_MAX, zlo = FLT_MAX, zhi = -FLT_MAX;
+  for (int k = lane; k < n; k += 64) {
+    const float y = in.y[g + k], z = in.z[g + k];
+    ylo = fminf(ylo, y); yhi = fmaxf(yhi, y);
+    zlo = fminf(zlo, z); zhi = fmaxf(zhi, z);
+  }
+  ylo = wave_min(ylo); yhi = wave_max(yhi);
+  zlo = wave_min(zlo); zhi = wave_max(zhi);
+  const int cap = min(2 * n + 1, kMaxBinsPerRow);
+  int target = (int)fminf(ceilf((float)n / bin_hits), (float)cap);
+  target = max(target, 1);
+  const float Ly = yhi - ylo, Lz = zhi - zlo;
+  int ny = 1, nz = 1;
+  if (Ly > 0.0f && Lz > 0.0f) {
+    const float w = sqrtf(Ly * Lz / (float)target);
+    ny = (int)fminf(ceilf(Ly / w), (float)target);
+    nz = (int)fminf(ceilf(Lz / w), (float)target);
+  } else if (Ly > 0.0f) {
+    ny = target;
+  } else if (Lz > 0.0f) {
+    nz = target;
+  }
+  ny = max(ny, 1);
+  nz = max(nz, 1);
+  if (ny * nz > cap) {
+    if (ny >= nz) ny = max(1, cap / nz); else nz = max(1, cap / ny);
+  }
+  const float iby = Ly > 0.0f ? (float)ny / Ly : 0.0f;
+  const float ibz = Lz > 0.0f ? (float)nz / Lz : 0.0f;
+  const float ymin = Ly > 0.0f ? ylo : 0.0f;
+  const float zmin = Lz > 0.0f ? zlo : 0.0f;
+  const int nb = ny * nz;
+  if (lane == 0) {
+    ws.grid_f[gid] = make_float4(ymin, zmin, iby, ibz);
+    ws.grid_n[gid] = make_int2(ny, nz);
+  }
+  for (int k = lane; k < nb; k += 64) cnt[k] = 0;
+  __syncthreads();
+  for (int k = lane; k < n; k += 64) {
+    const int b = bin_of(in.z[g + k], zmin, ibz, nz) * ny + bin_of(in.y[g + k], ymin, iby, ny);
+    atomicAdd(&cnt[b], 1);
+  }
+  __syncthreads();
+  // exclusive scan of cnt[0, nb): each lane owns a contiguous slice
+  const int per = (nb + 63) / 64;
+  const int b0 = min(nb, lane * per), b1 = min(nb, b0 + per);
+  int sum = 0;
+  for (int b = b0; b < b1; ++b) sum += cnt[b];
+  int incl = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o);
+    if (lane >= o) incl += v;
+  }
+  int run = incl - sum;
+  int32_t* bins = ws.bins + 2 * g + 2 * gid;
+  for (int b = b0; b < b1; ++b) {
+    const int c = cnt[b];
+    bins[b] = run;
+    cnt[b] = run;
+    run += c;
+  }
+  if (lane == 0) bins[nb] = n;
+  __syncthreads();
+  for (int k = lane; k < n; k += 64) {
+    const float y = in.y[g + k], z = in.z[g + k];
+    const int b = bin_of(z, zmin, ibz, nz) * ny + bin_of(y, ymin, iby, ny);
+    const int pos = atomicAdd(&cnt[b], 1);
+    SortedHit h;
+    h.y = y; h.z = z; h.idx = f0 + k; h.pad = 0;
+    ws.sorted[g + pos] = h;
+  }
+}
+
+// --------------------------------------------------------------- neighbours
+struct BinRange {
+  int y0, y1, z0, z1;
+};
+
+__device__ __forceinline__ BinRange bin_range(const RowGrid& G, float yc, float wy, float zc, float wz) {
+  BinRange b;
+  b.y0 = bin_of((yc - wy) - kBinMargin, G.ymin, G.iby, G.ny);
+  b.y1 = bin_of((yc + wy) + kBinMargin, G.ymin, G.iby, G.ny);
+  b.z0 = bin_of((zc - wz) - kBinMargin, G.zmin, G.ibz, G.nz);
+  b.z1 = bin_of((zc + wz) + kBinMargin, G.zmin, G.ibz, G.nz);
+  return b;
+}
+
+__global__ __launch_bounds__(256) void k_neighbours(Inputs in, Span sp, int R, const float* __restrict__ row_x,
+                                                    Consts c, Workspace ws, int32_t* __restrict__ out_up,
+                                                    int32_t* __restrict__ out_dn) {
+  const int64_t i = sp.h0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= sp.h1) return;
+  const int s = sector_of(in.hit_offset, sp.s0, sp.s1, i);
+  const int r = in.row[i];
+  int32_t bj = -1, bk = -1;
+  if (r >= 1 && r <= R - 2) {
+    const float xr = row_x[r], xu = row_x[r + 1], xd = row_x[r - 1];
+    const float fu = xu / xr;
+    const float fd = xd / xr;
+    const float t = (xr - xd) / (xu - xd);
+    const float yi = in.y[i], zi = in.z[i];
+    const float yu = yi * fu, zu = zi * fu;
+    const float yd = yi * fd, zd = zi * fd;
+    const RowGrid U = row_grid(in, ws, R, s, r + 1);
+    const RowGrid D = row_grid(in, ws, R, s, r - 1);
+    if (U.ny > 0 && D.ny > 0) {
+      const BinRange bu = bin_range(U, yu, c.wy, zu, c.wz);
+      const BinRange bd = bin_range(D, yd, c.wy, zd, c.wz);
+      float best = 0.0f;
+      for (int iz = bu.z0; iz <= bu.z1; ++iz) {
+        const int pe = U.bins[iz * U.ny + bu.y1 + 1];
+        for (int p = U.bins[iz * U.ny + bu.y0]; p < pe; ++p) {
+          const SortedHit hj = U.hits[p];
+          if (!(fabsf(hj.y - yu) <= c.wy && fabsf(hj.z - zu) <= c.wz)) continue;
+          for (int jz = bd.z0; jz <= bd.z1; ++jz) {
+            const int qe = D.bins[jz * D.ny + bd.y1 + 1];
+            for (int q = D.bins[jz * D.ny + bd.y0]; q < qe; ++q) {
+              const SortedHit hk = D.hits[q];
+              if (!(fabsf(hk.y - yd) <= c.wy && fabsf(hk.z - zd) <= c.wz)) continue;
+              const float ey = yi - (hk.y + t * (hj.y - hk.y));
+              const float ez = zi - (hk.z + t * (hj.z - hk.z));
+              const float chi2 = ey * ey + ez * ez;
+              if (!(chi2 <= c.chi2)) continue;
+              if (bj < 0 || chi2 < best || (chi2 == best && (hj.idx < bj || (hj.idx == bj && hk.idx < bk)))) {
+                best = chi2;
+                bj = hj.idx;
+                bk = hk.idx;
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  out_up[i] = bj;
+  out_dn[i] = bk;
+}
+
+// -------------------------------------------------------------- clean/start
+__global__ __launch_bounds__(kHitsPerBlock) void k_clean_start(Inputs in, Span sp, const int32_t* __restrict__ up,
+                                                               const int32_t* __restrict__ dn,
+                                                               int32_t* __restrict__ uc_out,
+                                                               int32_t* __restrict__ dc_out, Workspace ws) {
+  const int64_t i = sp.h0 + (int64_t)blockIdx.x * kHitsPerBlock + threadIdx.x;
+  bool start = false;
+  if (i < sp.h1) {
+    const int s = sector_of(in.hit_offset, sp.s0, sp.s1, i);
+    const int64_t a = in.hit_offset[s];
+    const int32_t me = (int32_t)(i - a);
+    const int32_t u = up[i], d = dn[i];
+    const int32_t uc = (u >= 0 && dn[a + u] == me) ? u : -1;
+    const int32_t dc = (d >= 0 && up[a + d] == me) ? d : -1;
+    if (dc < 0 && uc >= 0) {
+      const int32_t w = up[a + uc];
+      start = w >= 0 && dn[a + w] == uc;
+    }
+    uc_out[i] = uc;
+    dc_out[i] = dc;
+  }
+  const unsigned long long m = __ballot(start);
+  __shared__ int wc[kHitsPerBlock / 64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+    ws.start_mask[(int64_t)blockIdx.x * (kHitsPerBlock / 64) + wave] = m;
+    wc[wave] = __popcll(m);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < kHitsPerBlock / 64; ++w) t += wc[w];
+    ws.blk_cnt[blockIdx.x] = t;
+  }
+}
+
+// -------------------------------------------------------------------- scan
+__global__ __launch_bounds__(1024) void k_scan(Span sp, int64_t nblk, int64_t* toff, Workspace ws) {
+  __shared__ int64_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (nblk + 1023) / 1024;
+  const int64_t b0 = min(nblk, (int64_t)t * per), b1 = min(nblk, b0 + per);
+  int64_t sum = 0;
+  for (int64_t b = b0; b < b1; ++b) sum += ws.blk_cnt[b];
+  part[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int64_t v = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  const int64_t base = sp.s0 == 0 ? 0 : toff[sp.s0];
+  int64_t run = base + part[t] - sum;
+  for (int64_t b = b0; b < b1; ++b) {
+    ws.blk_off[b] = run;
+    run += ws.blk_cnt[b];
+  }
+  if (t == 1023) ws.blk_off[nblk] = base + part[1023];
+  if (t == 0) {
+    if (sp.s0 == 0) toff[0] = 0;
+    ws.counters[0] = 0ull;
+  }
+}
+
+// ----------------------------------------------------------------- compact
+__global__ __launch_bounds__(kHitsPerBlock) void k_compact(Inputs in, Span sp, int64_t nblk, int64_t* toff,
+                                                           int32_t* __restrict__ start_hit, Workspace ws) {
+  constexpr int W = kHitsPerBlock / 64;
+  if ((int64_t)blockIdx.x < nblk) {
+    const int64_t i = sp.h0 + (int64_t)blockIdx.x * kHitsPerBlock + threadIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const unsigned long long m = ws.start_mask[(int64_t)blockIdx.x * W + wave];
+    if (i < sp.h1 && ((m >> lane) & 1ull)) {
+      int64_t pos = ws.blk_off[blockIdx.x];
+      for (int w = 0; w < wave; ++w) pos += __popcll(ws.start_mask[(int64_t)blockIdx.x * W + w]);
+      pos += __popcll(m & ((1ull << lane) - 1ull));
+      const int s = sector_of(in.hit_offset, sp.s0, sp.s1, i);
+      start_hit[pos] = (int32_t)(i - in.hit_offset[s]);
+      ws.start_glob[pos] = (int32_t)i;
+    }
+  } else {
+    const int s = sp.s0 + 1 + (int)(((int64_t)blockIdx.x - nblk) * kHitsPerBlock + threadIdx.x);
+    if (s <= sp.s1) {
+      const int64_t j = in.hit_offset[s] - sp.h0;
+      const int64_t b = j / kHitsPerBlock;
+      int64_t p = ws.blk_off[b];
+      for (int64_t w = b * W; w < j / 64; ++w) p += __popcll(ws.start_mask[w]);
+      const int rem = (int)(j & 63);
+      if (rem) p += __popcll(ws.start_mask[j / 64] & ((1ull << rem) - 1ull));
+      toff[s] = p;
+    }
+  }
+}
+
+// ------------------------------------------------------------ Kalman filter
+struct Trk {
+  float x, y, z, s, l, q;
+  float c00, c10, c11, c20, c21, c22;
+  float d00, d10, d11;
+};
+
+enum { kStepOk = 0, kStepSinPhi = 1, kStepArc = 2 };
+
+__device__ __forceinline__ int init_track(Trk& t, float x0, float y0, float z0, float x1, float y1, float z1,
+                                          const Consts& c) {
+  const float dx = x1 - x0, dy = y1 - y0, dz = z1 - z0;
+  const float L = sqrtf(dx * dx + dy * dy);
+  t.x = x0; t.y = y0; t.z = z0;
+  t.s = dy / L;
+  t.l = dz / L;
+  t.q = 0.0f;
+  t.c00 = c.sy2; t.c10 = 0.0f; t.c11 = 1.0f; t.c20 = 0.0f; t.c21 = 0.0f; t.c22 = 100.0f;
+  t.d00 = c.sz2; t.d10 = 0.0f; t.d11 = 1.0f;
+  return fabsf(t.s) < 0.999f ? kStepOk : kStepSinPhi;
+}
+
+// Helix transport to x1 (constant field): exact state transport, arc length
+// from the asin(u)/u series through u^8, covariance C <- J C J^T per block.
+__device__ __forceinline__ int propagate(Trk& t, float x1, const Consts& c) {
+  const float dx = x1 - t.x;
+  const float k = c.kb * t.q;
+  const float s0 = t.s;
+  const float s1 = s0 + k * dx;
+  if (!(fabsf(s1) < 0.999f)) return kStepSinPhi;
+  const float c0 = sqrtf(1.0f - s0 * s0);
+  const float c1 = sqrtf(1.0f - s1 * s1);
+  const float T = (s0 + s1) / (c0 + c1);
+  const float dy = dx * T;
+  const float ch = sqrtf(dx * dx + dy * dy);
+  const float u = (k * ch) * 0.5f;
+  if (!(fabsf(u) <= 0.2f)) return kStepArc;
+  const float u2 = u * u;
+  const float A = 1.0f + u2 * (1.0f / 6.0f + u2 * (3.0f / 40.0f + u2 * (5.0f / 112.0f + u2 * (35.0f / 1152.0f))));
+  float dS = ch * A;
+  if (dx < 0.0f) dS = -dS;
+  const float sm = (s0 + s1) * 0.5f;
+  const float cm2 = 1.0f - sm * sm;
+  const float cm3 = cm2 * sqrtf(cm2);
+  const float a = dx / cm3;
+  const float b = ((c.kb * dx) * dx * 0.5f) / cm3;
+  const float d = c.kb * dx;
+  t.x = x1;
+  t.y = t.y + dy;
+  t.z = t.z + t.l * dS;
+  t.s = s1;
+  const float c00 = t.c00, c10 = t.c10, c11 = t.c11, c20 = t.c20, c21 = t.c21, c22 = t.c22;
+  const float m0 = c00 + a * c10 + b * c20;
+  const float m1 = c10 + a * c11 + b * c21;
+  const float m2 = c20 + a * c21 + b * c22;
+  const float n1 = c11 + d * c21;
+  const float n2 = c21 + d * c22;
+  t.c00 = m0 + a * m1 + b * m2;
+  t.c10 = m1 + d * m2;
+  t.c11 = n1 + d * n2;
+  t.c20 = m2;
+  t.c21 = n2;
+  const float tz = t.d10 + dS * t.d11;
+  t.d00 = t.d00 + dS * t.d10 + dS * tz;
+  t.d10 = tz;
+  return kStepOk;
+}
+
+// Kalman update with a cluster (my, mz): independent scalar updates of the
+// transverse (y, s, q) and longitudinal (z, l) blocks.
+__device__ __forceinline__ int update(Trk& t, float my, float mz, const Consts& c) {
+  const float ry = my - t.y;
+  const float Sy = t.c00 + c.sy2;
+  const float iy = 1.0f / Sy;
+  const float k0 = t.c00 * iy, k1 = t.c10 * iy, k2 = t.c20 * iy;
+  t.y = t.y + k0 * ry;
+  t.s = t.s + k1 * ry;
+  t.q = t.q + k2 * ry;
+  const float c00 = t.c00, c10 = t.c10, c20 = t.c20;
+  t.c00 = c00 - k0 * c00;
+  t.c10 = c10 - k1 * c00;
+  t.c20 = c20 - k2 * c00;
+  t.c11 = t.c11 - k1 * c10;
+  t.c21 = t.c21 - k2 * c10;
+  t.c22 = t.c22 - k2 * c20;
+  const float rz = mz - t.z;
+  const float Sz = t.d00 + c.sz2;
+  const float iz = 1.0f / Sz;
+  const float g0 = t.d00 * iz, g1 = t.d10 * iz;
+  t.z = t.z + g0 * rz;
+  t.l = t.l + g1 * rz;
+  const float d00 = t.d00, d10 = t.d10;
+  t.d00 = d00 - g0 * d00;
+  t.d10 = d10 - g1 * d00;
+  t.d11 = t.d11 - g1 * d10;
+  return fabsf(t.s) < 0.999f ? kStepOk : kStepSinPhi;
+}
+
+__device__ __forceinline__ bool spd_ok(const Trk& t) {
+  const float p0 = t.c00;
+  if (!(p0 > 0.0f && p0 <= FLT_MAX)) return false;
+  const float i0 = 1.0f / p0;
+  const float a = t.c10 * i0;
+  const float p1 = t.c11 - a * t.c10;
+  if (!(p1 > 0.0f && p1 <= FLT_MAX)) return false;
+  const float b = t.c20 * i0;
+  const float e = t.c21 - b * t.c10;
+  const float g = e / p1;
+  const float p2 = (t.c22 - b * t.c20) - g * e;
+  if (!(p2 > 0.0f && p2 <= FLT_MAX)) return false;
+  const float q0 = t.d00;
+  if (!(q0 > 0.0f && q0 <= FLT_MAX)) return false;
+  const float q1 = t.d11 - (t.d10 / q0) * t.d10;
+  if (!(q1 > 0.0f && q1 <= FLT_MAX)) return false;
+  return true;
+}
+
+// Closest gated cluster of a row: smallest dy^2 + dz^2, ties to the smaller
+// sector-local index; -1 if none.
+struct Work {
+  int n_prop, n_upd, n_cand, n_search;
+};
+
+__device__ __forceinline__ int32_t closest(const Trk& t, const RowGrid& G, const Consts& c, Work& w) {
+  const float gy = c.nsig * sqrtf(t.c00 + c.sy2);
+  const float gz = c.nsig * sqrtf(t.d00 + c.sz2);
+  int32_t best = -1;
+  ++w.n_search;
+  if (G.ny <= 0) return best;
+  const BinRange br = bin_range(G, t.y, gy, t.z, gz);
+  float bd = 0.0f;
+  for (int iz = br.z0; iz <= br.z1; ++iz) {
+    const int pe = G.bins[iz * G.ny + br.y1 + 1];
+    for (int p = G.bins[iz * G.ny + br.y0]; p < pe; ++p) {
+      const SortedHit h = G.hits[p];
+      const float dy = h.y - t.y;
+      const float dz = h.z - t.z;
+      if (!(fabsf(dy) <= gy && fabsf(dz) <= gz)) continue;
+      ++w.n_cand;
+      const float d2 = dy * dy + dz * dz;
+      if (best < 0 || d2 < bd || (d2 == bd && h.idx < best)) {
+        best = h.idx;
+        bd = d2;
+      }
+    }
+  }
+  return best;
+}
+
+__device__ __forceinline__ void store_state(const Trk& t, int64_t o, const TrackletOut& out) {
+  out.x_ref[o] = t.x;
+  float* p = out.param + 5 * o;
+  p[0] = t.y; p[1] = t.z; p[2] = t.s; p[3] = t.l; p[4] = t.q;
+  float* cv = out.cov + 15 * o;
+  cv[0] = t.c00; cv[1] = 0.0f; cv[2] = t.d00; cv[3] = t.c10; cv[4] = 0.0f;
+  cv[5] = t.c11; cv[6] = 0.0f; cv[7] = t.d10; cv[8] = 0.0f; cv[9] = t.d11;
+  cv[10] = t.c20; cv[11] = 0.0f; cv[12] = t.c21; cv[13] = 0.0f; cv[14] = t.c22;
+}
+
+__device__ __forceinline__ int stop_flag(int e) { return e == kStepSinPhi ? 2 : 4; }
+
+// One tracklet: slot -> start hit -> seed chain -> following -> output.
+__device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __restrict__ row_x, const Consts& c,
+                               const Workspace& ws, const int32_t* __restrict__ up_c, const int64_t* toff,
+                               int64_t slot, int64_t o, const TrackletOut& out, Work& w) {
+  const int s = sector_of(toff, sp.s0, sp.s1, slot);
+  const int64_t a = in.hit_offset[s];
+  const int64_t gi = ws.start_glob[slot];
+  const int32_t h0 = (int32_t)(gi - a);
+  const int r0 = in.row[gi];
+  const int32_t h1 = up_c[gi];
+  int32_t* rh = out.row_hit + o * R;
+  for (int r = 0; r < R; ++r) rh[r] = -1;
+  rh[r0] = h0;
+  int fl = 0;
+  int nh = 1, first_row = r0, lastr = r0;
+  Trk st, snap;
+  const int ei = init_track(st, row_x[r0], in.y[gi], in.z[gi], row_x[r0 + 1], in.y[a + h1], in.z[a + h1], c);
+  if (ei != kStepOk) {
+    fl |= stop_flag(ei);
+    snap = st;
+  } else {
+    Trk last = st;
+    // seed chain (no gate), then outward following
+    int32_t h = h1;
+    int miss = 0;
+    for (int r = r0 + 1; r < R; ++r) {
+      ++w.n_prop;
+      const int e = propagate(st, row_x[r], c);
+      if (e) { fl |= stop_flag(e); break; }
+      int32_t j = h;
+      if (j < 0) j = closest(st, row_grid(in, ws, R, s, r), c, w);
+      if (j >= 0) {
+        Trk u = st;
+        ++w.n_upd;
+        if (update(u, in.y[a + j], in.z[a + j], c)) { fl |= 2; break; }
+        st = u;
+        last = st;
+        lastr = r;
+        rh[r] = j;
+        ++nh;
+        miss = 0;
+        if (h >= 0) h = up_c[a + h];
+      } else if (++miss > c.max_miss) {
+        break;
+      }
+    }
+    // back to the start row without updates, then inward following
+    st = last;
+    snap = last;
+    miss = 0;
+    for (int r = lastr - 1; r >= 0; --r) {
+      ++w.n_prop;
+      const int e = propagate(st, row_x[r], c);
+      if (e) { fl |= stop_flag(e); break; }
+      if (r > r0) continue;
+      if (r == r0) { snap = st; continue; }
+      const int32_t j = closest(st, row_grid(in, ws, R, s, r), c, w);
+      if (j >= 0) {
+        Trk u = st;
+        ++w.n_upd;
+        if (update(u, in.y[a + j], in.z[a + j], c)) { fl |= 2; break; }
+        st = u;
+        snap = st;
+        rh[r] = j;
+        ++nh;
+        first_row = r;
+        miss = 0;
+      } else if (++miss > c.max_miss) {
+        break;
+      }
+    }
+  }
+  store_state(snap, o, out);
+  if (nh >= c.min_hits) fl |= 1;
+  if (!spd_ok(snap)) fl |= 8;
+  out.start_row[o] = r0;
+  out.first_row[o] = first_row;
+  out.last_row[o] = lastr;
+  out.n_hits[o] = nh;
+  out.flags[o] = fl;
+}
+
+__global__ __launch_bounds__(256) void k_tracklets(Inputs in, Span sp, int R, const float* __restrict__ row_x,
+                                                   Consts c, Workspace ws, const int32_t* __restrict__ up_c,
+                                                   const int64_t* toff, int64_t first, int64_t cap,
+                                                   TrackletOut out) {
+  const int64_t lo = max(toff[sp.s0], first);
+  const int64_t hi = min(toff[sp.s1], first + cap);
+  const int lane = threadIdx.x & 63;
+  Work w = {0, 0, 0, 0};
+  while (true) {
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&ws.counters[0], 64ull);
+    base = __shfl(base, 0);
+    const int64_t slot0 = lo + (int64_t)base;
+    if (slot0 >= hi) break;
+    const int64_t slot = slot0 + lane;
+    if (slot < hi) build_tracklet(in, sp, R, row_x, c, ws, up_c, toff, slot, slot - first, out, w);
+  }
+  // wave totals of the method-step counts (one atomic per wave and counter)
+  unsigned long long v[4] = {(unsigned long long)w.n_prop, (unsigned long long)w.n_upd,
+                             (unsigned long long)w.n_cand, (unsigned long long)w.n_search};
+  for (int k = 0; k < 4; ++k) {
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    if (lane == 0 && v[k]) atomicAdd(&ws.counters[2 + k], v[k]);
+  }
+}
+
+// ------------------------------------------------- binary64-covariance refit
+struct MTrk {
+  float x, y, z, s, l, q;
+  double c00, c10, c11, c20, c21, c22;
+  double d00, d10, d11;
+};
+
+__device__ __forceinline__ int prop_m(MTrk& t, float x1, float kb) {
+  const float dx = x1 - t.x;
+  const float k = kb * t.q;
+  const float s0 = t.s;
+  const float s1 = s0 + k * dx;
+  if (!(fabsf(s1) < 0.999f)) return kStepSinPhi;
+  const float c0 = sqrtf(1.0f - s0 * s0);
+  const float c1 = sqrtf(1.0f - s1 * s1);
+  const float T = (s0 + s1) / (c0 + c1);
+  const float dy = dx * T;
+  const float ch = sqrtf(dx * dx + dy * dy);
+  const float u = (k * ch) * 0.5f;
+  if (!(fabsf(u) <= 0.2f)) return kStepArc;
+  const float u2 = u * u;
+  const float A = 1.0f + u2 * (1.0f / 6.0f + u2 * (3.0f / 40.0f + u2 * (5.0f / 112.0f + u2 * (35.0f / 1152.0f))));
+  float dS = ch * A;
+  if (dx < 0.0f) dS = -dS;
+  const float sm = (s0 + s1) * 0.5f;
+  const float cm2 = 1.0f - sm * sm;
+  const float cm3 = cm2 * sqrtf(cm2);
+  const double a = (double)(dx / cm3);
+  const double b = (double)(((kb * dx) * dx * 0.5f) / cm3);
+  const double d = (double)(kb * dx);
+  const double e = (double)dS;
+  t.x = x1;
+  t.y = t.y + dy;
+  t.z = t.z + t.l * dS;
+  t.s = s1;
+  const double c00 = t.c00, c10 = t.c10, c11 = t.c11, c20 = t.c20, c21 = t.c21, c22 = t.c22;
+  const double m0 = c00 + a * c10 + b * c20;
+  const double m1 = c10 + a * c11 + b * c21;
+  const double m2 = c20 + a * c21 + b * c22;
+  const double n1 = c11 + d * c21;
+  const double n2 = c21 + d * c22;
+  t.c00 = m0 + a * m1 + b * m2;
+  t.c10 = m1 + d * m2;
+  t.c11 = n1 + d * n2;
+  t.c20 = m2;
+  t.c21 = n2;
+  const double tz = t.d10 + e * t.d11;
+  t.d00 = t.d00 + e * t.d10 + e * tz;
+  t.d10 = tz;
+  return kStepOk;
+}
+
+__device__ __forceinline__ int upd_m(MTrk& t, float my, float mz, double sy2, double sz2) {
+  const float ry = my - t.y;
+  const double iy = 1.0 / (t.c00 + sy2);
+  const double k0 = t.c00 * iy, k1 = t.c10 * iy, k2 = t.c20 * iy;
+  t.y = t.y + (float)(k0 * (double)ry);
+  t.s = t.s + (float)(k1 * (double)ry);
+  t.q = t.q + (float)(k2 * (double)ry);
+  const double c00 = t.c00, c10 = t.c10, c20 = t.c20;
+  t.c00 = c00 - k0 * c00;
+  t.c10 = c10 - k1 * c00;
+  t.c20 = c20 - k2 * c00;
+  t.c11 = t.c11 - k1 * c10;
+  t.c21 = t.c21 - k2 * c10;
+  t.c22 = t.c22 - k2 * c20;
+  const float rz = mz - t.z;
+  const double iz = 1.0 / (t.d00 + sz2);
+  const double g0 = t.d00 * iz, g1 = t.d10 * iz;
+  t.z = t.z + (float)(g0 * (double)rz);
+  t.l = t.l + (float)(g1 * (double)rz);
+  const double d00 = t.d00, d10 = t.d10;
+  t.d00 = d00 - g0 * d00;
+  t.d10 = d10 - g1 * d00;
+  t.d11 = t.d11 - g1 * d10;
+  return fabsf(t.s) < 0.999f ? kStepOk : kStepSinPhi;
+}
+
+__global__ __launch_bounds__(256) void k_refit64(Inputs in, Span sp, int R, const float* __restrict__ row_x,
+                                                 Consts c, const int64_t* toff, int64_t first, int64_t cap,
+                                                 TrackletOut out) {
+  const int64_t lo = max(toff[sp.s0], first);
+  const int64_t hi = min(toff[sp.s1], first + cap);
+  for (int64_t slot = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; slot < hi;
+       slot += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = slot - first;
+    const int fl = out.flags[o];
+    if (!((c.precision == 1 && (fl & 8)) || c.precision == 2)) continue;
+    const int s = sector_of(toff, sp.s0, sp.s1, slot);
+    const int64_t a = in.hit_offset[s];
+    const int32_t* rh = out.row_hit + o * R;
+    const int r0 = out.start_row[o];
+    MTrk st = {};
+    MTrk snap;
+    bool ok = r0 >= 0 && r0 + 1 < R && rh[r0] >= 0 && rh[r0 + 1] >= 0;
+    if (ok) {
+      const int32_t h0 = rh[r0], h1 = rh[r0 + 1];
+      const float x0 = row_x[r0], x1 = row_x[r0 + 1];
+      const float dx = x1 - x0, dy = in.y[a + h1] - in.y[a + h0], dz = in.z[a + h1] - in.z[a + h0];
+      const float L = sqrtf(dx * dx + dy * dy);
+      st.x = x0; st.y = in.y[a + h0]; st.z = in.z[a + h0]; st.s = dy / L; st.l = dz / L; st.q = 0.0f;
+      st.c00 = c.sy2d; st.c10 = 0.0; st.c11 = 1.0; st.c20 = 0.0; st.c21 = 0.0; st.c22 = 100.0;
+      st.d00 = c.sz2d; st.d10 = 0.0; st.d11 = 1.0;
+      ok = fabsf(st.s) < 0.999f;
+    }
+    snap = st;
+    if (ok) {
+      int lastr = r0, fr = r0;
+      for (int r = r0 + 1; r < R; ++r) if (rh[r] >= 0) lastr = r;
+      for (int r = r0 - 1; r >= 0; --r) if (rh[r] >= 0) fr = r;
+      MTrk last = st;
+      int lr = r0;
+      for (int r = r0 + 1; r <= lastr; ++r) {
+        if (prop_m(st, row_x[r], c.kb)) break;
+        if (rh[r] >= 0) {
+          MTrk u = st;
+          if (upd_m(u, in.y[a + rh[r]], in.z[a + rh[r]], c.sy2d, c.sz2d)) break;
+          st = u; last = st; lr = r;
+        }
+      }
+      st = last;
+      bool back = true;
+      for (int r = lr - 1; r >= r0; --r)
+        if (prop_m(st, row_x[r], c.kb)) { back = false; break; }
+      snap = back ? st : last;
+      if (back) {
+        for (int r = r0 - 1; r >= fr; --r) {
+          if (prop_m(st, row_x[r], c.kb)) break;
+          if (rh[r] >= 0) {
+            MTrk u = st;
+            if (upd_m(u, in.y[a + rh[r]], in.z[a + rh[r]], c.sy2d, c.sz2d)) break;
+            st = u; snap = st;
+          }
+        }
+      }
+    }
+    out.x_ref[o] = snap.x;
+    float* p = out.param + 5 * o;
+    p[0] = snap.y; p[1] = snap.z; p[2] = snap.s; p[3] = snap.l; p[4] = snap.q;
+    float* cv = out.cov + 15 * o;
+    cv[0] = (float)snap.c00; cv[1] = 0.0f; cv[2] = (float)snap.d00; cv[3] = (float)snap.c10; cv[4] = 0.0f;
+    cv[5] = (float)snap.c11; cv[6] = 0.0f; cv[7] = (float)snap.d10; cv[8] = 0.0f; cv[9] = (float)snap.d11;
+    cv[10] = (float)snap.c20; cv[11] = 0.0f; cv[12] = (float)snap.c21; cv[13] = 0.0f; cv[14] = (float)snap.c22;
+    out.flags[o] = fl | 16;
+  }
+}
+
+// ------------------------------------------------------------------ probe
+__global__ void k_fp32_probe(int op, const float* a, const float* b, float* o, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float x = a[i], y = b[i];
+  float r;
+  switch (op) {
+    case 0: r = x + y; break;
+    case 1: r = x - y; break;
+    case 2: r = x * y; break;
+    case 3: r = x / y; break;
+    default: r = sqrtf(x); break;
+  }
+  o[i] = r;
+}
+
+inline unsigned blocks_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+}  // namespace
+
+// ================================================================ launchers
+hipError_t launch_reset(unsigned long long* counters, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, counters, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_index(const Inputs& in, Span sp, int n_rows, const Workspace& ws, int block, hipStream_t st) {
+  const int64_t n_items = (int64_t)(sp.s1 - sp.s0) * (n_rows + 1);
+  const int64_t total = n_items + (sp.h1 - sp.h0);
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_index, dim3(blocks_for(total, block)), dim3(block), 0, st, in, sp, n_rows,
+                     ws.row_first, ws.counters, n_items);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid(const Inputs& in, Span sp, int n_rows, float bin_hits, const Workspace& ws, hipStream_t st) {
+  const int64_t items = (int64_t)(sp.s1 - sp.s0) * n_rows;
+  if (items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_grid, dim3((unsigned)items), dim3(64), 0, st, in, sp, n_rows, bin_hits, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_neighbours(const Inputs& in, Span sp, int n_rows, const float* row_x, const Consts& c,
+                             const Workspace& ws, int32_t* up, int32_t* dn, int block, hipStream_t st) {
+  const int64_t n = sp.h1 - sp.h0;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_neighbours, dim3(blocks_for(n, block)), dim3(block), 0, st, in, sp, n_rows, row_x, c, ws,
+                     up, dn);
+  return hipGetLastError();
+}
+
+hipError_t launch_clean_start(const Inputs& in, Span sp, const int32_t* up, const int32_t* dn, int32_t* up_c,
+                              int32_t* dn_c, const Workspace& ws, hipStream_t st) {
+  const int64_t n = sp.h1 - sp.h0;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_clean_start, dim3(blocks_for(n, kHitsPerBlock)), dim3(kHitsPerBlock), 0, st, in, sp, up, dn,
+                     up_c, dn_c, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(Span sp, int64_t* toff, const Workspace& ws, hipStream_t st) {
+  const int64_t nblk = (sp.h1 - sp.h0 + kHitsPerBlock - 1) / kHitsPerBlock;
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, sp, nblk, toff, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const Inputs& in, Span sp, int64_t* toff, int32_t* start_hit, const Workspace& ws,
+                          hipStream_t st) {
+  const int64_t nblk = (sp.h1 - sp.h0 + kHitsPerBlock - 1) / kHitsPerBlock;
+  const int64_t nsec_blk = ((int64_t)(sp.s1 - sp.s0) + kHitsPerBlock - 1) / kHitsPerBlock;
+  const int64_t grid = nblk + nsec_blk;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_compact, dim3((unsigned)grid), dim3(kHitsPerBlock), 0, st, in, sp, nblk, toff, start_hit, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_tracklets(const Inputs& in, Span sp, int n_rows, const float* row_x, const Consts& c,
+                            const Workspace& ws, const int32_t* up_c, const int64_t* toff, int64_t first,
+                            int64_t cap, const TrackletOut& out, int grid, int block, hipStream_t st) {
+  hipLaunchKernelGGL(k_tracklets, dim3(grid), dim3(block), 0, st, in, sp, n_rows, row_x, c, ws, up_c, toff, first,
+                     cap, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_refit64(const Inputs& in, Span sp, int n_rows, const float* row_x, const Consts& c,
+                          const Workspace& ws, const int64_t* toff, int64_t first, int64_t cap,
+                          const TrackletOut& out, int grid, hipStream_t st) {
+  (void)ws;
+  hipLaunchKernelGGL(k_refit64, dim3(grid), dim3(256), 0, st, in, sp, n_rows, row_x, c, toff, first, cap, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fp32_probe(int op, const float* a, const float* b, float* out, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fp32_probe, dim3(blocks_for(n, 256)), dim3(256), 0, st, op, a, b, out, n);
+  return hipGetLastError();
+}
+
+}  // namespace catpc
