@@ -92,8 +92,13 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--cpu-hits", type=float, default=6e6, help="oracle sample size for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tuning", default=None, help="JSON file with catpc tuning values")
+    ap.add_argument("--tuning", default="auto",
+                    help="'auto' (the autotuner's cache for this architecture, if present), 'default', or a JSON "
+                         "file with catpc tuning values")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="launch the chain directly (for counter runs)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="before the timed region, one device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the hot path shards by event with no "
@@ -115,8 +120,30 @@ def main():
     torch.cuda.set_stream(stream)
     hits = DeviceHits(batch.y, batch.z, batch.row, batch.hit_offset, dev)
     tr = Tracker(batch.row_x, hits.n_hits, hits.n_sectors, device=dev)
-    if args.tuning:
+    tuning_src = "library defaults"
+    if args.tuning == "auto":
+        from paper_1712_09430_amd import autotune
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+        if os.path.exists(autotune.DEFAULT_CACHE):
+            cache = json.load(open(autotune.DEFAULT_CACHE))
+            if cache.get("arch", "").split(":")[0] == arch:
+                tr.set_tuning(cache["tuning"])
+                tuning_src = "autotuner cache " + os.path.basename(autotune.DEFAULT_CACHE)
+    elif args.tuning != "default":
         tr.set_tuning(json.load(open(args.tuning)))
+        tuning_src = args.tuning
+    if args.no_graph:
+        tr.set_tuning({"use_graph": 0})
+    t = C.catpc_get_tuning(tr.ctx)
+    tuning = {f: getattr(t, f) for f, _ in C.catpc_tuning._fields_}
+    if args.copy_mib > 0:
+        n = args.copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.copy_mib} MiB done")
+        del src, dst
     out = tr.output(hits)
     log(f"[bench] {hits.n_hits} hits in {hits.n_sectors} sectors; warmup {args.warmup}")
 
@@ -193,7 +220,8 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded helix events, no recorded data)",
            "config": {"workload": desc, "n_hits": hits.n_hits, "n_sectors": hits.n_sectors,
                       "n_tracklets": n_trk, "seed": args.seed, "form": "batched: fixed launch chain over all "
-                      "sectors, persistent tracklet kernel, hipGraph replay", "parallelism": "single GPU"},
+                      "sectors, persistent tracklet kernel, hipGraph replay", "parallelism": "single GPU",
+                      "tuning": tuning, "tuning_source": tuning_src},
            "plain": plain, "batched_over_plain": (value / plain["hits_per_s"]) if plain else None,
            "stages_ms": stages, "roofline": {k: v for k, v in dominant.items() if k != "kernel"} |
            {"kernel": dominant["kernel"]}, "rooflines": {"k_tracklets": rl_tc, "k_neighbours": rl_nf},

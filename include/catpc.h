@@ -72,8 +72,14 @@ typedef struct {
   float bin_hits;        /* target hits per grid bin [2.0] */
   int32_t nf_block;      /* threads per workgroup of the per-hit kernels [256] */
   int32_t tc_block;      /* threads per workgroup of the tracklet kernel [256] */
-  int32_t tc_waves_per_cu; /* resident waves per CU of the persistent tracklet kernel [8] */
+  int32_t tc_waves_per_cu; /* resident waves per CU of the persistent tracklet kernel [20] */
   int32_t use_graph;     /* 1: replay the batched stage chain as a captured hipGraph [1] */
+  int32_t tc_refill;     /* 1: a lane takes the next tracklet as soon as its own is done;
+                            0: a wave takes 64 tracklets at a time [0] */
+  int32_t nf_rows;       /* pad rows per neighbour-finder workgroup (row chunk) [4] */
+  int32_t nf_lds_kb;     /* LDS budget (KiB) for staging a row chunk and its two neighbour rows [32] */
+  int32_t tc_xcd;        /* 1: tracklet slots split into one contiguous part per die, each die starting on its
+                            own part (L2 locality) [1] */
 } catpc_tuning;
 
 /* Input hits (device pointers). */

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/catpc.h"
 #include "internal.h"
@@ -36,7 +37,7 @@ catpc_status hip_fail(hipError_t e, const char* what) {
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t row_first, grid_f, grid_n, bins, sorted, raw_up, raw_dn, mask, blk_cnt, blk_off, start_glob, counters;
+  size_t row_first, hdr, bins, sorted, raw_up, raw_dn, mask, blk_cnt, blk_off, start_glob, chain, counters;
   size_t total;
 };
 
@@ -46,8 +47,7 @@ Layout plan(int32_t R, int64_t H, int32_t S) {
   auto take = [&](size_t bytes) { size_t p = o; o += align_up(bytes); return p; };
   const size_t nblk = (size_t)(H / kHitsPerBlock) + 8;
   L.row_first = take(sizeof(int32_t) * (size_t)S * (R + 1));
-  L.grid_f = take(sizeof(float4) * (size_t)S * R);
-  L.grid_n = take(sizeof(int2) * (size_t)S * R);
+  L.hdr = take(sizeof(RowHdr) * (size_t)S * R);
   L.bins = take(sizeof(int32_t) * (2 * (size_t)H + 2 * (size_t)S * R + 8));
   L.sorted = take(sizeof(SortedHit) * (size_t)(H + 1));
   L.raw_up = take(sizeof(int32_t) * (size_t)(H + 1));
@@ -56,7 +56,8 @@ Layout plan(int32_t R, int64_t H, int32_t S) {
   L.blk_cnt = take(sizeof(int32_t) * (nblk + 8));
   L.blk_off = take(sizeof(int64_t) * (nblk + 8));
   L.start_glob = take(sizeof(int32_t) * (size_t)(H + 1));
-  L.counters = take(sizeof(unsigned long long) * 8);
+  L.chain = take(sizeof(ChainHit) * (size_t)(H + 1));
+  L.counters = take(sizeof(unsigned long long) * kNumCounters);
   L.total = o;
   return L;
 }
@@ -79,6 +80,7 @@ struct catpc_ctx {
   int64_t max_hits = 0;
   int32_t max_sectors = 0;
   float* row_x = nullptr;  // device [n_rows]
+  float4* rowk = nullptr;  // device [n_rows]: x_{r+1}/x_r, x_{r-1}/x_r, chord weight, 0 (binary32 divisions)
   catpc_params params{};
   catpc_tuning tuning{};
   Consts consts{};
@@ -205,7 +207,8 @@ catpc_status enqueue_span(catpc_ctx* ctx, const catpc_input* in, const catpc_out
   HIP_TRY(mark(1));
   HIP_TRY(launch_grid(I, sp, ctx->n_rows, ctx->tuning.bin_hits, ws, st));
   HIP_TRY(mark(2));
-  HIP_TRY(launch_neighbours(I, sp, ctx->n_rows, ctx->row_x, ctx->consts, ws, up, dn, nb, st));
+  HIP_TRY(launch_neighbours(I, sp, ctx->n_rows, ctx->rowk, ctx->consts, ws, up, dn, nb, ctx->tuning.nf_rows,
+                            ctx->tuning.nf_lds_kb * 1024, st));
   HIP_TRY(mark(3));
   HIP_TRY(launch_clean_start(I, sp, up, dn, out->link_up, out->link_dn, ws, st));
   HIP_TRY(mark(4));
@@ -214,9 +217,9 @@ catpc_status enqueue_span(catpc_ctx* ctx, const catpc_input* in, const catpc_out
   HIP_TRY(launch_compact(I, sp, out->tracklet_offset, out->start_hit, ws, st));
   HIP_TRY(mark(6));
   if (out->tracklet_capacity > 0) {
-    HIP_TRY(launch_tracklets(I, sp, ctx->n_rows, ctx->row_x, ctx->consts, ws, out->link_up, out->tracklet_offset, 0,
+    HIP_TRY(launch_tracklets(I, sp, ctx->n_rows, ctx->row_x, ctx->consts, ws, out->tracklet_offset, 0,
                              out->tracklet_capacity, tracklets_of(out), tc_grid(ctx, (sp.h1 - sp.h0) / 3 + 1),
-                             ctx->tuning.tc_block, st));
+                             ctx->tuning.tc_block, ctx->tuning.tc_refill, ctx->tuning.tc_xcd ? kXcds : 1, st));
   }
   HIP_TRY(mark(7));
   return CATPC_OK;
@@ -231,7 +234,7 @@ catpc_status enqueue_refit(catpc_ctx* ctx, const catpc_input* in, const catpc_ou
 }
 
 catpc_status enqueue_batch(catpc_ctx* ctx, const catpc_input* in, const catpc_output* out, hipStream_t st) {
-  HIP_TRY(launch_reset(ctx->ws.counters, 8, st));
+  HIP_TRY(launch_reset(ctx->ws.counters, kNumCounters, st));
   if (in->n_sectors == 0) return CATPC_OK;
   Span sp{0, in->n_sectors, 0, in->n_hits};
   catpc_status rc = enqueue_span(ctx, in, out, sp, st);
@@ -270,13 +273,17 @@ void catpc_default_tuning(catpc_tuning* t) {
   t->bin_hits = 2.0f;
   t->nf_block = 256;
   t->tc_block = 256;
-  t->tc_waves_per_cu = 8;
+  t->tc_waves_per_cu = 20;
   t->use_graph = 1;
+  t->tc_refill = 0;
+  t->nf_rows = 4;
+  t->nf_lds_kb = 32;
+  t->tc_xcd = 1;
 }
 
 size_t catpc_workspace_bytes(int32_t n_rows, int64_t max_hits, int32_t max_sectors) {
   if (n_rows < 3 || max_hits < 0 || max_sectors < 0) return 0;
-  return plan(n_rows, max_hits, max_sectors).total + sizeof(float) * (size_t)n_rows;
+  return plan(n_rows, max_hits, max_sectors).total + (sizeof(float) + sizeof(float4)) * (size_t)n_rows;
 }
 
 const char* catpc_last_error(void) { return g_err.c_str(); }
@@ -290,8 +297,8 @@ catpc_status catpc_create(int32_t n_rows, const float* row_x, const catpc_params
     if (!(row_x[r] > 0.0f) || (r > 0 && !(row_x[r] > row_x[r - 1])))
       return fail(CATPC_E_INVALID, "row_x must be positive and strictly ascending");
   if (max_hits < 0 || max_hits >= (int64_t)1 << 31) return fail(CATPC_E_INVALID, "max_hits out of [0, 2^31)");
-  if (max_sectors < 0 || (int64_t)max_sectors * n_rows >= (int64_t)1 << 31)
-    return fail(CATPC_E_INVALID, "max_sectors out of range");
+  if (max_sectors < 0 || max_hits + (int64_t)max_sectors * n_rows >= (int64_t)1 << 31)
+    return fail(CATPC_E_INVALID, "max_hits + max_sectors * n_rows must stay below 2^31");
   catpc_status rc = check_params(params);
   if (rc) return rc;
   catpc_ctx* ctx = new (std::nothrow) catpc_ctx();
@@ -311,15 +318,31 @@ catpc_status catpc_create(int32_t n_rows, const float* row_x, const catpc_params
     e = hipMalloc(&ctx->ws_mem, L.total);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->row_x, sizeof(float) * (size_t)n_rows);
     if (e == hipSuccess) e = hipMemcpy(ctx->row_x, row_x, sizeof(float) * (size_t)n_rows, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->host_counters, sizeof(unsigned long long) * 8, 0);
+    if (e == hipSuccess) {
+      // per-row neighbour-finder ratios, each one binary32 division as in the
+      // per-hit formula (hoisted: they depend on the row only)
+      std::vector<float4> k((size_t)n_rows);
+      for (int32_t r = 0; r < n_rows; ++r) {
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, row_x[r]);
+        if (r >= 1 && r + 1 < n_rows) {
+          const float xr = row_x[r], xu = row_x[r + 1], xd = row_x[r - 1];
+          v.x = xu / xr;
+          v.y = xd / xr;
+          v.z = (xr - xd) / (xu - xd);
+        }
+        k[(size_t)r] = v;
+      }
+      e = hipMalloc((void**)&ctx->rowk, sizeof(float4) * (size_t)n_rows);
+      if (e == hipSuccess) e = hipMemcpy(ctx->rowk, k.data(), sizeof(float4) * (size_t)n_rows, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->host_counters, sizeof(unsigned long long) * kNumCounters, 0);
     if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->host_total, sizeof(int64_t), 0);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
     if (e == hipSuccess) {
       char* b = (char*)ctx->ws_mem;
       Workspace& w = ctx->ws;
       w.row_first = (int32_t*)(b + L.row_first);
-      w.grid_f = (float4*)(b + L.grid_f);
-      w.grid_n = (int2*)(b + L.grid_n);
+      w.hdr = (RowHdr*)(b + L.hdr);
       w.bins = (int32_t*)(b + L.bins);
       w.sorted = (SortedHit*)(b + L.sorted);
       w.raw_up = (int32_t*)(b + L.raw_up);
@@ -328,8 +351,9 @@ catpc_status catpc_create(int32_t n_rows, const float* row_x, const catpc_params
       w.blk_cnt = (int32_t*)(b + L.blk_cnt);
       w.blk_off = (int64_t*)(b + L.blk_off);
       w.start_glob = (int32_t*)(b + L.start_glob);
+      w.chain = (ChainHit*)(b + L.chain);
       w.counters = (unsigned long long*)(b + L.counters);
-      e = hipMemset(w.counters, 0, sizeof(unsigned long long) * 8);
+      e = hipMemset(w.counters, 0, sizeof(unsigned long long) * kNumCounters);
     }
   }
   if (e != hipSuccess) {
@@ -345,6 +369,7 @@ void catpc_destroy(catpc_ctx* ctx) {
   drop_graph(ctx);
   if (ctx->ws_mem) (void)hipFree(ctx->ws_mem);
   if (ctx->row_x) (void)hipFree(ctx->row_x);
+  if (ctx->rowk) (void)hipFree(ctx->rowk);
   if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
   if (ctx->host_total) (void)hipHostFree(ctx->host_total);
   if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
@@ -368,6 +393,11 @@ catpc_status catpc_set_tuning(catpc_ctx* ctx, const catpc_tuning* t) {
   if (t->tc_block < 64 || t->tc_block > 256 || t->tc_block % 64)
     return fail(CATPC_E_INVALID, "tc_block must be a multiple of 64 in [64, 256]");
   if (t->tc_waves_per_cu < 1 || t->tc_waves_per_cu > 32) return fail(CATPC_E_INVALID, "tc_waves_per_cu out of [1, 32]");
+  if (t->use_graph < 0 || t->use_graph > 1 || t->tc_refill < 0 || t->tc_refill > 1)
+    return fail(CATPC_E_INVALID, "use_graph and tc_refill must be 0 or 1");
+  if (t->nf_rows < 1 || t->nf_rows > 32) return fail(CATPC_E_INVALID, "nf_rows out of [1, 32]");
+  if (t->nf_lds_kb < 0 || t->nf_lds_kb > 64) return fail(CATPC_E_INVALID, "nf_lds_kb out of [0, 64]");
+  if (t->tc_xcd < 0 || t->tc_xcd > 1) return fail(CATPC_E_INVALID, "tc_xcd must be 0 or 1");
   ctx->tuning = *t;
   return CATPC_OK;
 }
@@ -435,7 +465,7 @@ catpc_status catpc_track_plain(catpc_ctx* ctx, const catpc_input* in, const catp
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(ctx->device));
   ctx->have_last = false;
-  HIP_TRY(launch_reset(ctx->ws.counters, 8, st));
+  HIP_TRY(launch_reset(ctx->ws.counters, kNumCounters, st));
   const int64_t* h = in->hit_offset_host;
   for (int32_t s = 0; s < in->n_sectors; ++s) {
     Span sp{s, s + 1, h[s], h[s + 1]};
@@ -458,7 +488,7 @@ catpc_status catpc_result(catpc_ctx* ctx, void* stream, int64_t* n_tracklets) {
   if (!ctx->have_last) return fail(CATPC_E_STATE, "no completed track call");
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(ctx->device));
-  HIP_TRY(hipMemcpyAsync(ctx->host_counters, ctx->ws.counters, sizeof(unsigned long long) * 8,
+  HIP_TRY(hipMemcpyAsync(ctx->host_counters, ctx->ws.counters, sizeof(unsigned long long) * kNumCounters,
                          hipMemcpyDeviceToHost, st));
   int64_t total = 0;
   if (ctx->last_in.n_sectors > 0) {
@@ -468,7 +498,7 @@ catpc_status catpc_result(catpc_ctx* ctx, void* stream, int64_t* n_tracklets) {
   HIP_TRY(hipStreamSynchronize(st));
   if (ctx->last_in.n_sectors > 0) total = *ctx->host_total;
   if (n_tracklets) *n_tracklets = total;
-  if (ctx->host_counters[1] & 1ull) return fail(CATPC_E_INVALID, "hits not sorted by row, or a row out of range");
+  if (ctx->host_counters[kCtrError] & 1ull) return fail(CATPC_E_INVALID, "hits not sorted by row, or a row out of range");
   if (total > ctx->last_out.tracklet_capacity)
     return fail(CATPC_E_CAPACITY, "more tracklets (" + std::to_string(total) + ") than output slots (" +
                                       std::to_string(ctx->last_out.tracklet_capacity) + ")");
@@ -494,10 +524,10 @@ catpc_status catpc_fetch_tracklets(catpc_ctx* ctx, const catpc_input* in, int64_
   const Inputs I = inputs_of(in);
   catpc_output o = *out;
   o.tracklet_offset = ctx->last_out.tracklet_offset;
-  HIP_TRY(launch_reset(ctx->ws.counters, 1, st));
-  HIP_TRY(launch_tracklets(I, sp, ctx->n_rows, ctx->row_x, ctx->consts, ctx->ws, ctx->last_out.link_up,
-                           o.tracklet_offset, first, o.tracklet_capacity, tracklets_of(&o), tc_grid(ctx),
-                           ctx->tuning.tc_block, st));
+  HIP_TRY(launch_reset(ctx->ws.counters, kXcds, st));
+  HIP_TRY(launch_tracklets(I, sp, ctx->n_rows, ctx->row_x, ctx->consts, ctx->ws, o.tracklet_offset, first,
+                           o.tracklet_capacity, tracklets_of(&o), tc_grid(ctx), ctx->tuning.tc_block,
+                           ctx->tuning.tc_refill, ctx->tuning.tc_xcd ? kXcds : 1, st));
   return enqueue_refit(ctx, in, &o, sp, first, st);
 }
 
@@ -511,7 +541,7 @@ catpc_status catpc_stage_times(catpc_ctx* ctx, const catpc_input* in, const catp
   ctx->have_last = false;
   hipEvent_t ev[CATPC_N_STAGES + 1] = {};
   for (int k = 0; k <= CATPC_N_STAGES; ++k) HIP_TRY(hipEventCreate(&ev[k]));
-  HIP_TRY(launch_reset(ctx->ws.counters, 8, st));
+  HIP_TRY(launch_reset(ctx->ws.counters, kNumCounters, st));
   const Span sp{0, in->n_sectors, 0, in->n_hits};
   if (in->n_sectors > 0) {
     rc = enqueue_span(ctx, in, out, sp, st, ev);
@@ -536,10 +566,10 @@ catpc_status catpc_work_counts(catpc_ctx* ctx, void* stream, int64_t* counts) {
   if (!ctx || !counts) return fail(CATPC_E_INVALID, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(ctx->device));
-  HIP_TRY(hipMemcpyAsync(ctx->host_counters, ctx->ws.counters, sizeof(unsigned long long) * 8,
+  HIP_TRY(hipMemcpyAsync(ctx->host_counters, ctx->ws.counters, sizeof(unsigned long long) * kNumCounters,
                          hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  for (int k = 0; k < 4; ++k) counts[k] = (int64_t)ctx->host_counters[2 + k];
+  for (int k = 0; k < 4; ++k) counts[k] = (int64_t)ctx->host_counters[kCtrCounts + k];
   return CATPC_OK;
 }
 

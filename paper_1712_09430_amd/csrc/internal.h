@@ -7,11 +7,31 @@
 
 namespace catpc {
 
-// Grid-sorted hit: position in the row grid, sector-local input index.
+// Grid-sorted hit: position, sector-local input index, pad row.
 struct alignas(16) SortedHit {
   float y, z;
   int32_t idx;
+  int32_t row;
+};
+
+// Per-hit record in input order, written by the link-cleaning stage: the
+// coordinates and the cleaned upward link, so that a step along a seed chain
+// reads one 16-byte record.
+struct alignas(16) ChainHit {
+  float y, z;
+  int32_t up;
   int32_t pad;
+};
+
+// Per (sector, row) grid header, one 32-byte record: bin origin and bins per
+// cm, bin counts (ny == 0: empty row), global position of the row's first
+// sorted hit, and half the offset of its bin table (the table sits at
+// 2 * (first hit + row id), always even).
+struct alignas(32) RowHdr {
+  float ymin, zmin, iby, ibz;
+  int32_t ny, nz;
+  int32_t hit_base;
+  int32_t bin_half;
 };
 
 // Method constants, every value already rounded the way the filter uses it.
@@ -29,8 +49,7 @@ struct Consts {
 
 struct Workspace {
   int32_t* row_first;    // [S*(R+1)] sector-local first hit of each row (row-major by sector)
-  float4* grid_f;        // [S*R] per row: y_min, z_min, bins per cm in y, in z
-  int2* grid_n;          // [S*R] per row: bins in y, in z (0 = empty row)
+  RowHdr* hdr;           // [S*R] per row grid header
   int32_t* bins;         // [2H + 2SR] per row: first sorted position of each bin, then n_row
   SortedHit* sorted;     // [H] hits in bin order per row
   int32_t* raw_up;       // [H] neighbour-finder links when the caller does not keep them
@@ -39,8 +58,15 @@ struct Workspace {
   int32_t* blk_cnt;      // [H/256 + 8] start hits per block
   int64_t* blk_off;      // [H/256 + 8] first slot of each block
   int32_t* start_glob;   // [H] global hit index of each tracklet slot
-  unsigned long long* counters; // [8]: 0 work counter, 1 error bits
+  ChainHit* chain;       // [H] coordinates + cleaned up-link per hit (input order)
+  unsigned long long* counters; // [kNumCounters], see kCtr*
 };
+
+constexpr int kXcds = 8;         // MI355X: 8 accelerator dies, workgroups dispatched round-robin over them
+constexpr int kCtrWork = 0;      // [0, kXcds): work counters of the tracklet kernel, one per slot partition
+constexpr int kCtrError = 8;     // bit 0: invalid rows seen
+constexpr int kCtrCounts = 9;    // [9, 13): transports, updates, gated candidates, row searches
+constexpr int kNumCounters = 16;
 
 // Call geometry: sectors [s0, s1), hits [h0, h1) (global indices).
 struct Span {
@@ -75,16 +101,17 @@ constexpr float kBinMargin = 1.0e-2f;  // cm, widens bin ranges beyond rounding 
 hipError_t launch_reset(unsigned long long* counters, int n, hipStream_t st);
 hipError_t launch_row_index(const Inputs& in, Span sp, int n_rows, const Workspace& ws, int block, hipStream_t st);
 hipError_t launch_grid(const Inputs& in, Span sp, int n_rows, float bin_hits, const Workspace& ws, hipStream_t st);
-hipError_t launch_neighbours(const Inputs& in, Span sp, int n_rows, const float* row_x, const Consts& c,
-                             const Workspace& ws, int32_t* up, int32_t* dn, int block, hipStream_t st);
+hipError_t launch_neighbours(const Inputs& in, Span sp, int n_rows, const float4* rowk, const Consts& c,
+                             const Workspace& ws, int32_t* up, int32_t* dn, int block, int rows, int lds_bytes,
+                             hipStream_t st);
 hipError_t launch_clean_start(const Inputs& in, Span sp, const int32_t* up, const int32_t* dn, int32_t* up_c,
                               int32_t* dn_c, const Workspace& ws, hipStream_t st);
 hipError_t launch_scan(Span sp, int64_t* toff, const Workspace& ws, hipStream_t st);
 hipError_t launch_compact(const Inputs& in, Span sp, int64_t* toff, int32_t* start_hit, const Workspace& ws,
                           hipStream_t st);
 hipError_t launch_tracklets(const Inputs& in, Span sp, int n_rows, const float* row_x, const Consts& c,
-                            const Workspace& ws, const int32_t* up_c, const int64_t* toff, int64_t first,
-                            int64_t cap, const TrackletOut& out, int grid, int block, hipStream_t st);
+                            const Workspace& ws, const int64_t* toff, int64_t first, int64_t cap,
+                            const TrackletOut& out, int grid, int block, int refill, int nparts, hipStream_t st);
 hipError_t launch_refit64(const Inputs& in, Span sp, int n_rows, const float* row_x, const Consts& c,
                           const Workspace& ws, const int64_t* toff, int64_t first, int64_t cap,
                           const TrackletOut& out, int grid, hipStream_t st);

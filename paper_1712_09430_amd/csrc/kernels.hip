@@ -50,6 +50,18 @@ __device__ __forceinline__ int bin_of(float v, float vmin, float inv, int n) {
   return (int)f;
 }
 
+// Sector of hit i, for the threads of a block whose hits start at `first`
+// (first <= i): one binary search per block, broadcast through LDS, then a
+// short forward walk.  Every thread of the block must call it.
+__device__ __forceinline__ int block_sector(const int64_t* off, int s0, int s1, int64_t first, int64_t i) {
+  __shared__ int s_first;
+  if (threadIdx.x == 0) s_first = sector_of(off, s0, s1, first);
+  __syncthreads();
+  int s = s_first;
+  while (s + 1 < s1 && off[s + 1] <= i) ++s;
+  return s;
+}
+
 struct RowGrid {
   float ymin, zmin, iby, ibz;
   int ny, nz;
@@ -57,19 +69,14 @@ struct RowGrid {
   const SortedHit* hits;
 };
 
-__device__ __forceinline__ RowGrid row_grid(const Inputs& in, const Workspace& ws, int R, int s, int r) {
+__device__ __forceinline__ RowGrid row_grid(const Workspace& ws, int R, int s, int r) {
+  const RowHdr h = ws.hdr[(int64_t)s * R + r];
   RowGrid G;
-  const int64_t gid = (int64_t)s * R + r;
-  const int2 nn = ws.grid_n[gid];
-  G.ny = nn.x;
-  G.nz = nn.y;
-  if (G.ny > 0) {
-    const float4 f = ws.grid_f[gid];
-    G.ymin = f.x; G.zmin = f.y; G.iby = f.z; G.ibz = f.w;
-    const int64_t g = in.hit_offset[s] + ws.row_first[(int64_t)s * (R + 1) + r];
-    G.bins = ws.bins + 2 * g + 2 * gid;
-    G.hits = ws.sorted + g;
-  }
+  G.ymin = h.ymin; G.zmin = h.zmin; G.iby = h.iby; G.ibz = h.ibz;
+  G.ny = h.ny;
+  G.nz = h.nz;
+  G.bins = ws.bins + 2 * (int64_t)h.bin_half;
+  G.hits = ws.sorted + h.hit_base;
   return G;
 }
 
@@ -79,10 +86,16 @@ __global__ void k_reset(unsigned long long* c, int n) {
 }
 
 // --------------------------------------------------------------- row index
+// Blocks [0, item_blocks): one thread per (sector, row 0..R) item, first hit
+// of the row by binary search (monotone in r for any input; row 0 starts at
+// the sector's first hit and row R at its end, so the rows always partition
+// the sector).  Remaining blocks: one thread per hit, order and range check.
 __global__ __launch_bounds__(256) void k_row_index(Inputs in, Span sp, int R, int32_t* row_first,
-                                                   unsigned long long* counters, int64_t n_items) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < n_items) {
+                                                   unsigned long long* counters, int64_t n_items,
+                                                   int64_t item_blocks) {
+  if ((int64_t)blockIdx.x < item_blocks) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_items) return;
     const int s = sp.s0 + (int)(g / (R + 1));
     const int r = (int)(g % (R + 1));
     const int64_t a = in.hit_offset[s], b = in.hit_offset[s + 1];
@@ -91,15 +104,16 @@ __global__ __launch_bounds__(256) void k_row_index(Inputs in, Span sp, int R, in
       const int64_t mid = (lo + hi) >> 1;
       if (in.row[mid] < r) lo = mid + 1; else hi = mid;
     }
-    row_first[(int64_t)s * (R + 1) + r] = (int32_t)((r == R ? b : lo) - a);
+    row_first[(int64_t)s * (R + 1) + r] = (int32_t)((r == R ? b : r == 0 ? a : lo) - a);
   } else {
-    const int64_t i = sp.h0 + (g - n_items);
+    const int64_t first = sp.h0 + ((int64_t)blockIdx.x - item_blocks) * blockDim.x;
+    const int64_t i = first + threadIdx.x;
+    const int s = block_sector(in.hit_offset, sp.s0, sp.s1, first, min(i, sp.h1 - 1));
     if (i < sp.h1) {
-      const int s = sector_of(in.hit_offset, sp.s0, sp.s1, i);
       const int32_t r = in.row[i];
       bool ok = r >= 0 && r < R;
       if (i > in.hit_offset[s]) ok = ok && in.row[i - 1] <= r;
-      if (!ok) atomicOr(&counters[1], 1ull);
+      if (!ok) atomicOr(&counters[kCtrError], 1ull);
     }
   }
 }
@@ -125,11 +139,14 @@ __global__ __launch_bounds__(64) void k_grid(Inputs in, Span sp, int R, float bi
   const int32_t f0 = ws.row_first[(int64_t)s * (R + 1) + r];
   const int32_t f1 = ws.row_first[(int64_t)s * (R + 1) + r + 1];
   const int n = f1 - f0;
+  const int64_t g = a + f0;
   if (n <= 0) {
-    if (lane == 0) ws.grid_n[gid] = make_int2(0, 0);
+    if (lane == 0) {
+      RowHdr h = {0.0f, 0.0f, 0.0f, 0.0f, 0, 0, (int32_t)g, (int32_t)(g + gid)};
+      ws.hdr[gid] = h;
+    }
     return;
   }
-  const int64_t g = a + f0;
   float ylo = FLT_MAX, yhi = -FLT_MAX, zlo = FLT_MAX, zhi = -FLT_MAX;
   for (int k = lane; k < n; k += 64) {
     const float y = in.y[g + k], z = in.z[g + k];
@@ -163,8 +180,8 @@ __global__ __launch_bounds__(64) void k_grid(Inputs in, Span sp, int R, float bi
   const float zmin = Lz > 0.0f ? zlo : 0.0f;
   const int nb = ny * nz;
   if (lane == 0) {
-    ws.grid_f[gid] = make_float4(ymin, zmin, iby, ibz);
-    ws.grid_n[gid] = make_int2(ny, nz);
+    RowHdr h = {ymin, zmin, iby, ibz, ny, nz, (int32_t)g, (int32_t)(g + gid)};
+    ws.hdr[gid] = h;
   }
   for (int k = lane; k < nb; k += 64) cnt[k] = 0;
   __syncthreads();
@@ -198,7 +215,7 @@ __global__ __launch_bounds__(64) void k_grid(Inputs in, Span sp, int R, float bi
     const int b = bin_of(z, zmin, ibz, nz) * ny + bin_of(y, ymin, iby, ny);
     const int pos = atomicAdd(&cnt[b], 1);
     SortedHit h;
-    h.y = y; h.z = z; h.idx = f0 + k; h.pad = 0;
+    h.y = y; h.z = z; h.idx = f0 + k; h.row = r;
     ws.sorted[g + pos] = h;
   }
 }
@@ -217,55 +234,149 @@ __device__ __forceinline__ BinRange bin_range(const RowGrid& G, float yc, float 
   return b;
 }
 
-__global__ __launch_bounds__(256) void k_neighbours(Inputs in, Span sp, int R, const float* __restrict__ row_x,
+constexpr int kNfKeep = 8;
+
+// Score the pair (up j, down k) for the hit (yi, zi) and keep the
+// lexicographic minimum of (chi2, j, k) among pairs within the cut.
+__device__ __forceinline__ void nf_consider(float yi, float zi, float t, float chi2max, float yj, float zj,
+                                            int32_t j, float yk, float zk, int32_t k, float& best, int32_t& bj,
+                                            int32_t& bk) {
+  const float ey = yi - (yk + t * (yj - yk));
+  const float ez = zi - (zk + t * (zj - zk));
+  const float chi2 = ey * ey + ez * ez;
+  if (!(chi2 <= chi2max)) return;
+  if (bj < 0 || chi2 < best || (chi2 == best && (j < bj || (j == bj && k < bk)))) {
+    best = chi2;
+    bj = j;
+    bk = k;
+  }
+}
+
+// Grid of row rr of sector s, pointing into the LDS copy when the row is
+// inside the staged range.
+struct Stage {
+  int r_lo, r_hi;         // staged rows [r_lo, r_hi]
+  int64_t hit0, bin0;     // global sorted position / bin-table offset of the first staged row
+  const SortedHit* hits;  // LDS
+  const int32_t* bins;    // LDS
+  bool on;
+};
+
+__device__ __forceinline__ RowGrid staged_grid(const Workspace& ws, int R, int s, int rr, const Stage& S) {
+  RowGrid G = row_grid(ws, R, s, rr);
+  if (S.on && rr >= S.r_lo && rr <= S.r_hi) {
+    G.hits = S.hits + (G.hits - (ws.sorted + S.hit0));
+    G.bins = S.bins + (G.bins - (ws.bins + S.bin0));
+  }
+  return G;
+}
+
+// One workgroup per (sector, chunk of `rows` pad rows); its lanes take the
+// chunk's hits in grid order (all rows of the chunk together, so sparse rows
+// do not leave lanes idle).  The chunk's rows and the row on each side are
+// contiguous in the grid-sorted array and in the bin tables; they are staged
+// in LDS when they fit in `lds_bytes` (dynamic shared memory), else read in
+// place.  Down-row candidates inside the window are kept in registers (up to
+// kNfKeep; beyond that the down row is scanned again per up candidate).  Hits
+// of rows 0 and R-1 get -1 links.  rowk[r] = (x_{r+1}/x_r, x_{r-1}/x_r,
+// (x_r - x_{r-1}) / (x_{r+1} - x_{r-1})), each one binary32 division.
+__global__ __launch_bounds__(256) void k_neighbours(Inputs in, Span sp, int R, const float4* __restrict__ rowk,
                                                     Consts c, Workspace ws, int32_t* __restrict__ out_up,
-                                                    int32_t* __restrict__ out_dn) {
-  const int64_t i = sp.h0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= sp.h1) return;
-  const int s = sector_of(in.hit_offset, sp.s0, sp.s1, i);
-  const int r = in.row[i];
-  int32_t bj = -1, bk = -1;
-  if (r >= 1 && r <= R - 2) {
-    const float xr = row_x[r], xu = row_x[r + 1], xd = row_x[r - 1];
-    const float fu = xu / xr;
-    const float fd = xd / xr;
-    const float t = (xr - xd) / (xu - xd);
-    const float yi = in.y[i], zi = in.z[i];
-    const float yu = yi * fu, zu = zi * fu;
-    const float yd = yi * fd, zd = zi * fd;
-    const RowGrid U = row_grid(in, ws, R, s, r + 1);
-    const RowGrid D = row_grid(in, ws, R, s, r - 1);
-    if (U.ny > 0 && D.ny > 0) {
-      const BinRange bu = bin_range(U, yu, c.wy, zu, c.wz);
-      const BinRange bd = bin_range(D, yd, c.wy, zd, c.wz);
-      float best = 0.0f;
-      for (int iz = bu.z0; iz <= bu.z1; ++iz) {
-        const int pe = U.bins[iz * U.ny + bu.y1 + 1];
-        for (int p = U.bins[iz * U.ny + bu.y0]; p < pe; ++p) {
-          const SortedHit hj = U.hits[p];
-          if (!(fabsf(hj.y - yu) <= c.wy && fabsf(hj.z - zu) <= c.wz)) continue;
-          for (int jz = bd.z0; jz <= bd.z1; ++jz) {
-            const int qe = D.bins[jz * D.ny + bd.y1 + 1];
-            for (int q = D.bins[jz * D.ny + bd.y0]; q < qe; ++q) {
-              const SortedHit hk = D.hits[q];
-              if (!(fabsf(hk.y - yd) <= c.wy && fabsf(hk.z - zd) <= c.wz)) continue;
-              const float ey = yi - (hk.y + t * (hj.y - hk.y));
-              const float ez = zi - (hk.z + t * (hj.z - hk.z));
-              const float chi2 = ey * ey + ez * ez;
-              if (!(chi2 <= c.chi2)) continue;
-              if (bj < 0 || chi2 < best || (chi2 == best && (hj.idx < bj || (hj.idx == bj && hk.idx < bk)))) {
-                best = chi2;
-                bj = hj.idx;
-                bk = hk.idx;
+                                                    int32_t* __restrict__ out_dn, int rows, int lds_bytes) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int chunks = (R + rows - 1) / rows;
+  const int s = sp.s0 + (int)(blockIdx.x / chunks);
+  const int c0 = (int)(blockIdx.x % chunks) * rows;
+  const int c1 = min(R, c0 + rows);
+  const int32_t* rf = ws.row_first + (int64_t)s * (R + 1);
+  const int n = rf[c1] - rf[c0];
+  if (n <= 0) return;
+  const int64_t a = in.hit_offset[s];
+  Stage S;
+  S.on = false;
+  S.r_lo = max(c0 - 1, 0);
+  S.r_hi = min(c1, R - 1);
+  const SortedHit* own = ws.sorted + a + rf[c0];
+  {
+    const int64_t h0 = a + rf[S.r_lo], h1 = a + rf[S.r_hi + 1];
+    const int64_t b0 = 2 * (h0 + (int64_t)s * R + S.r_lo);
+    const int64_t b1 = 2 * (h1 + (int64_t)s * R + S.r_hi + 1);
+    const int64_t nh = h1 - h0, nb = b1 - b0;
+    if (nh * (int64_t)sizeof(SortedHit) + nb * (int64_t)sizeof(int32_t) <= lds_bytes) {
+      SortedHit* lh = reinterpret_cast<SortedHit*>(lds);
+      int32_t* lb = reinterpret_cast<int32_t*>(lds + nh * sizeof(SortedHit));
+      for (int k = threadIdx.x; k < nh; k += blockDim.x) lh[k] = ws.sorted[h0 + k];
+      for (int k = threadIdx.x; k < nb; k += blockDim.x) lb[k] = ws.bins[b0 + k];
+      __syncthreads();
+      S.on = true;
+      S.hit0 = h0;
+      S.bin0 = b0;
+      S.hits = lh;
+      S.bins = lb;
+      own = lh + (a + rf[c0] - h0);
+    }
+  }
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const SortedHit me = own[k];
+    const int r = me.row;
+    int32_t bj = -1, bk = -1;
+    if (r >= 1 && r <= R - 2) {
+      const RowGrid U = staged_grid(ws, R, s, r + 1, S);
+      const RowGrid D = staged_grid(ws, R, s, r - 1, S);
+      if (U.ny > 0 && D.ny > 0) {
+        const float4 f = rowk[r];
+        const float fu = f.x, fd = f.y, t = f.z;
+        const float yi = me.y, zi = me.z;
+        const float yu = yi * fu, zu = zi * fu;
+        const float yd = yi * fd, zd = zi * fd;
+        const BinRange ru = bin_range(U, yu, c.wy, zu, c.wz);
+        const BinRange rd = bin_range(D, yd, c.wy, zd, c.wz);
+        float ky[kNfKeep], kz[kNfKeep];
+        int32_t ki[kNfKeep];
+        int nk = 0;
+        bool spill = false;
+        for (int jz = rd.z0; jz <= rd.z1; ++jz) {
+          const int qe = D.bins[jz * D.ny + rd.y1 + 1];
+          for (int q = D.bins[jz * D.ny + rd.y0]; q < qe; ++q) {
+            const SortedHit hk = D.hits[q];
+            if (!(fabsf(hk.y - yd) <= c.wy && fabsf(hk.z - zd) <= c.wz)) continue;
+#pragma unroll
+            for (int m = 0; m < kNfKeep; ++m)
+              if (m == nk) { ky[m] = hk.y; kz[m] = hk.z; ki[m] = hk.idx; }
+            spill = spill || nk == kNfKeep;
+            nk = min(nk + 1, kNfKeep);
+          }
+        }
+        float best = 0.0f;
+        if (nk > 0) {
+          for (int iz = ru.z0; iz <= ru.z1; ++iz) {
+            const int pe = U.bins[iz * U.ny + ru.y1 + 1];
+            for (int p = U.bins[iz * U.ny + ru.y0]; p < pe; ++p) {
+              const SortedHit hj = U.hits[p];
+              if (!(fabsf(hj.y - yu) <= c.wy && fabsf(hj.z - zu) <= c.wz)) continue;
+              if (!spill) {
+#pragma unroll
+                for (int m = 0; m < kNfKeep; ++m)
+                  if (m < nk) nf_consider(yi, zi, t, c.chi2, hj.y, hj.z, hj.idx, ky[m], kz[m], ki[m], best, bj, bk);
+              } else {
+                for (int jz = rd.z0; jz <= rd.z1; ++jz) {
+                  const int qe = D.bins[jz * D.ny + rd.y1 + 1];
+                  for (int q = D.bins[jz * D.ny + rd.y0]; q < qe; ++q) {
+                    const SortedHit hk = D.hits[q];
+                    if (!(fabsf(hk.y - yd) <= c.wy && fabsf(hk.z - zd) <= c.wz)) continue;
+                    nf_consider(yi, zi, t, c.chi2, hj.y, hj.z, hj.idx, hk.y, hk.z, hk.idx, best, bj, bk);
+                  }
+                }
               }
             }
           }
         }
       }
     }
+    const int64_t i = a + me.idx;
+    out_up[i] = bj;
+    out_dn[i] = bk;
   }
-  out_up[i] = bj;
-  out_dn[i] = bk;
 }
 
 // -------------------------------------------------------------- clean/start
@@ -273,10 +384,11 @@ __global__ __launch_bounds__(kHitsPerBlock) void k_clean_start(Inputs in, Span s
                                                                const int32_t* __restrict__ dn,
                                                                int32_t* __restrict__ uc_out,
                                                                int32_t* __restrict__ dc_out, Workspace ws) {
-  const int64_t i = sp.h0 + (int64_t)blockIdx.x * kHitsPerBlock + threadIdx.x;
+  const int64_t first = sp.h0 + (int64_t)blockIdx.x * kHitsPerBlock;
+  const int64_t i = first + threadIdx.x;
+  const int s = block_sector(in.hit_offset, sp.s0, sp.s1, first, min(i, sp.h1 - 1));
   bool start = false;
   if (i < sp.h1) {
-    const int s = sector_of(in.hit_offset, sp.s0, sp.s1, i);
     const int64_t a = in.hit_offset[s];
     const int32_t me = (int32_t)(i - a);
     const int32_t u = up[i], d = dn[i];
@@ -288,6 +400,12 @@ __global__ __launch_bounds__(kHitsPerBlock) void k_clean_start(Inputs in, Span s
     }
     uc_out[i] = uc;
     dc_out[i] = dc;
+    ChainHit ch;
+    ch.y = in.y[i];
+    ch.z = in.z[i];
+    ch.up = uc;
+    ch.pad = 0;
+    ws.chain[i] = ch;
   }
   const unsigned long long m = __ballot(start);
   __shared__ int wc[kHitsPerBlock / 64];
@@ -329,7 +447,7 @@ __global__ __launch_bounds__(1024) void k_scan(Span sp, int64_t nblk, int64_t* t
   if (t == 1023) ws.blk_off[nblk] = base + part[1023];
   if (t == 0) {
     if (sp.s0 == 0) toff[0] = 0;
-    ws.counters[0] = 0ull;
+    for (int k = 0; k < kXcds; ++k) ws.counters[kCtrWork + k] = 0ull;
   }
 }
 
@@ -338,14 +456,15 @@ __global__ __launch_bounds__(kHitsPerBlock) void k_compact(Inputs in, Span sp, i
                                                            int32_t* __restrict__ start_hit, Workspace ws) {
   constexpr int W = kHitsPerBlock / 64;
   if ((int64_t)blockIdx.x < nblk) {
-    const int64_t i = sp.h0 + (int64_t)blockIdx.x * kHitsPerBlock + threadIdx.x;
+    const int64_t first = sp.h0 + (int64_t)blockIdx.x * kHitsPerBlock;
+    const int64_t i = first + threadIdx.x;
+    const int s = block_sector(in.hit_offset, sp.s0, sp.s1, first, min(i, sp.h1 - 1));
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const unsigned long long m = ws.start_mask[(int64_t)blockIdx.x * W + wave];
     if (i < sp.h1 && ((m >> lane) & 1ull)) {
       int64_t pos = ws.blk_off[blockIdx.x];
       for (int w = 0; w < wave; ++w) pos += __popcll(ws.start_mask[(int64_t)blockIdx.x * W + w]);
       pos += __popcll(m & ((1ull << lane) - 1ull));
-      const int s = sector_of(in.hit_offset, sp.s0, sp.s1, i);
       start_hit[pos] = (int32_t)(i - in.hit_offset[s]);
       ws.start_glob[pos] = (int32_t)i;
     }
@@ -480,16 +599,22 @@ __device__ __forceinline__ bool spd_ok(const Trk& t) {
   return true;
 }
 
-// Closest gated cluster of a row: smallest dy^2 + dz^2, ties to the smaller
-// sector-local index; -1 if none.
 struct Work {
   int n_prop, n_upd, n_cand, n_search;
 };
 
-__device__ __forceinline__ int32_t closest(const Trk& t, const RowGrid& G, const Consts& c, Work& w) {
+// A cluster: sector-local index (-1: none) and its coordinates.
+struct Pick {
+  int32_t idx;
+  float y, z;
+};
+
+// Closest gated cluster of a row: smallest dy^2 + dz^2, ties to the smaller
+// sector-local index.
+__device__ __forceinline__ Pick closest(const Trk& t, const RowGrid& G, const Consts& c, Work& w) {
   const float gy = c.nsig * sqrtf(t.c00 + c.sy2);
   const float gz = c.nsig * sqrtf(t.d00 + c.sz2);
-  int32_t best = -1;
+  Pick best = {-1, 0.0f, 0.0f};
   ++w.n_search;
   if (G.ny <= 0) return best;
   const BinRange br = bin_range(G, t.y, gy, t.z, gz);
@@ -503,13 +628,25 @@ __device__ __forceinline__ int32_t closest(const Trk& t, const RowGrid& G, const
       if (!(fabsf(dy) <= gy && fabsf(dz) <= gz)) continue;
       ++w.n_cand;
       const float d2 = dy * dy + dz * dz;
-      if (best < 0 || d2 < bd || (d2 == bd && h.idx < best)) {
-        best = h.idx;
+      if (best.idx < 0 || d2 < bd || (d2 == bd && h.idx < best.idx)) {
+        best.idx = h.idx;
+        best.y = h.y;
+        best.z = h.z;
         bd = d2;
       }
     }
   }
   return best;
+}
+
+__device__ __forceinline__ RowGrid grid_of(const RowHdr& h, const Workspace& ws) {
+  RowGrid G;
+  G.ymin = h.ymin; G.zmin = h.zmin; G.iby = h.iby; G.ibz = h.ibz;
+  G.ny = h.ny;
+  G.nz = h.nz;
+  G.bins = ws.bins + 2 * (int64_t)h.bin_half;
+  G.hits = ws.sorted + h.hit_base;
+  return G;
 }
 
 __device__ __forceinline__ void store_state(const Trk& t, int64_t o, const TrackletOut& out) {
@@ -524,23 +661,86 @@ __device__ __forceinline__ void store_state(const Trk& t, int64_t o, const Track
 
 __device__ __forceinline__ int stop_flag(int e) { return e == kStepSinPhi ? 2 : 4; }
 
+// Wave totals of the method-step counts (one atomic per wave and counter).
+__device__ __forceinline__ void flush_work(const Work& w, const Workspace& ws, int lane) {
+  unsigned long long v[4] = {(unsigned long long)w.n_prop, (unsigned long long)w.n_upd,
+                             (unsigned long long)w.n_cand, (unsigned long long)w.n_search};
+  for (int k = 0; k < 4; ++k) {
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    if (lane == 0 && v[k]) atomicAdd(&ws.counters[kCtrCounts + k], v[k]);
+  }
+}
+
+// Slot partitions of the persistent tracklet kernels.  With nparts == kXcds
+// the slot range is cut into kXcds contiguous parts and a workgroup starts on
+// the part of the die it runs on (workgroups are dispatched round-robin over
+// the dies), so the row grids a die's L2 holds belong to fewer sectors; a
+// wave whose part is used up continues with the following parts.
+struct Parts {
+  int64_t lo, hi, len;
+  int nparts, home;
+};
+
+__device__ __forceinline__ Parts make_parts(int64_t lo, int64_t hi, int nparts) {
+  Parts P;
+  P.lo = lo;
+  P.hi = hi;
+  P.nparts = nparts;
+  P.len = (hi - lo + nparts - 1) / nparts;
+  P.home = (int)(blockIdx.x % (unsigned)nparts);
+  return P;
+}
+
+// Wave-uniform: take `want` consecutive slots from the current part (index k,
+// advanced past used-up parts).  Returns the first slot and the part's end,
+// or -1 when every part is used up.
+__device__ __forceinline__ int64_t take_slots(const Parts& P, int& k, unsigned long long* ctr, int want, int lane,
+                                              int64_t& part_end) {
+  while (k < P.nparts) {
+    const int part = (P.home + k) % P.nparts;
+    const int64_t plo = P.lo + (int64_t)part * P.len;
+    const int64_t phi = min(P.hi, plo + P.len);
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&ctr[part], (unsigned long long)want);
+    base = __shfl(base, 0);
+    const int64_t s0 = plo + (int64_t)base;
+    if (s0 < phi) {
+      part_end = phi;
+      return s0;
+    }
+    ++k;
+  }
+  return -1;
+}
+
+// Start of a tracklet: its start hit (slot -> global hit), the chain record
+// of the start hit and of its upward neighbour, the seed state.
+struct Seed {
+  int64_t a;
+  int s, r0;
+  int32_t h0, h1, h2;  // start hit, its up neighbour, the one after (chain continues there)
+  float y1, z1;
+};
+
 // One tracklet: slot -> start hit -> seed chain -> following -> output.
 __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __restrict__ row_x, const Consts& c,
-                               const Workspace& ws, const int32_t* __restrict__ up_c, const int64_t* toff,
-                               int64_t slot, int64_t o, const TrackletOut& out, Work& w) {
+                               const Workspace& ws, const int64_t* toff, int64_t slot, int64_t o,
+                               const TrackletOut& out, Work& w) {
   const int s = sector_of(toff, sp.s0, sp.s1, slot);
   const int64_t a = in.hit_offset[s];
   const int64_t gi = ws.start_glob[slot];
   const int32_t h0 = (int32_t)(gi - a);
   const int r0 = in.row[gi];
-  const int32_t h1 = up_c[gi];
+  const ChainHit c0 = ws.chain[gi];
+  const int32_t h1 = c0.up;
+  ChainHit nx = ws.chain[a + h1];  // next chain measurement
   int32_t* rh = out.row_hit + o * R;
   for (int r = 0; r < R; ++r) rh[r] = -1;
   rh[r0] = h0;
   int fl = 0;
   int nh = 1, first_row = r0, lastr = r0;
   Trk st, snap;
-  const int ei = init_track(st, row_x[r0], in.y[gi], in.z[gi], row_x[r0 + 1], in.y[a + h1], in.z[a + h1], c);
+  const int ei = init_track(st, row_x[r0], c0.y, c0.z, row_x[r0 + 1], nx.y, nx.z, c);
   if (ei != kStepOk) {
     fl |= stop_flag(ei);
     snap = st;
@@ -550,22 +750,31 @@ __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __
     int32_t h = h1;
     int miss = 0;
     for (int r = r0 + 1; r < R; ++r) {
+      RowHdr hd;
+      if (h < 0) hd = ws.hdr[(int64_t)s * R + r];  // issued before the transport arithmetic
       ++w.n_prop;
       const int e = propagate(st, row_x[r], c);
       if (e) { fl |= stop_flag(e); break; }
-      int32_t j = h;
-      if (j < 0) j = closest(st, row_grid(in, ws, R, s, r), c, w);
-      if (j >= 0) {
+      Pick j;
+      if (h >= 0) {
+        j.idx = h; j.y = nx.y; j.z = nx.z;
+      } else {
+        j = closest(st, grid_of(hd, ws), c, w);
+      }
+      if (j.idx >= 0) {
         Trk u = st;
         ++w.n_upd;
-        if (update(u, in.y[a + j], in.z[a + j], c)) { fl |= 2; break; }
+        if (update(u, j.y, j.z, c)) { fl |= 2; break; }
         st = u;
         last = st;
         lastr = r;
-        rh[r] = j;
+        rh[r] = j.idx;
         ++nh;
         miss = 0;
-        if (h >= 0) h = up_c[a + h];
+        if (h >= 0) {
+          h = nx.up;
+          if (h >= 0) nx = ws.chain[a + h];
+        }
       } else if (++miss > c.max_miss) {
         break;
       }
@@ -575,19 +784,21 @@ __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __
     snap = last;
     miss = 0;
     for (int r = lastr - 1; r >= 0; --r) {
+      RowHdr hd;
+      if (r < r0) hd = ws.hdr[(int64_t)s * R + r];
       ++w.n_prop;
       const int e = propagate(st, row_x[r], c);
       if (e) { fl |= stop_flag(e); break; }
       if (r > r0) continue;
       if (r == r0) { snap = st; continue; }
-      const int32_t j = closest(st, row_grid(in, ws, R, s, r), c, w);
-      if (j >= 0) {
+      const Pick j = closest(st, grid_of(hd, ws), c, w);
+      if (j.idx >= 0) {
         Trk u = st;
         ++w.n_upd;
-        if (update(u, in.y[a + j], in.z[a + j], c)) { fl |= 2; break; }
+        if (update(u, j.y, j.z, c)) { fl |= 2; break; }
         st = u;
         snap = st;
-        rh[r] = j;
+        rh[r] = j.idx;
         ++nh;
         first_row = r;
         miss = 0;
@@ -607,29 +818,183 @@ __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __
 }
 
 __global__ __launch_bounds__(256) void k_tracklets(Inputs in, Span sp, int R, const float* __restrict__ row_x,
-                                                   Consts c, Workspace ws, const int32_t* __restrict__ up_c,
-                                                   const int64_t* toff, int64_t first, int64_t cap,
-                                                   TrackletOut out) {
+                                                   Consts c, Workspace ws, const int64_t* toff, int64_t first,
+                                                   int64_t cap, TrackletOut out, int nparts) {
   const int64_t lo = max(toff[sp.s0], first);
   const int64_t hi = min(toff[sp.s1], first + cap);
   const int lane = threadIdx.x & 63;
   Work w = {0, 0, 0, 0};
+  const Parts P = make_parts(lo, hi, nparts);
+  int k = 0;
   while (true) {
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(&ws.counters[0], 64ull);
-    base = __shfl(base, 0);
-    const int64_t slot0 = lo + (int64_t)base;
-    if (slot0 >= hi) break;
+    int64_t pend = 0;
+    const int64_t slot0 = take_slots(P, k, ws.counters + kCtrWork, 64, lane, pend);
+    if (slot0 < 0) break;
     const int64_t slot = slot0 + lane;
-    if (slot < hi) build_tracklet(in, sp, R, row_x, c, ws, up_c, toff, slot, slot - first, out, w);
+    if (slot < pend) build_tracklet(in, sp, R, row_x, c, ws, toff, slot, slot - first, out, w);
   }
-  // wave totals of the method-step counts (one atomic per wave and counter)
-  unsigned long long v[4] = {(unsigned long long)w.n_prop, (unsigned long long)w.n_upd,
-                             (unsigned long long)w.n_cand, (unsigned long long)w.n_search};
-  for (int k = 0; k < 4; ++k) {
-    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
-    if (lane == 0 && v[k]) atomicAdd(&ws.counters[2 + k], v[k]);
+  flush_work(w, ws, lane);
+}
+
+// Same tracklets, one row step per loop iteration for every lane, and a lane
+// whose tracklet is finished takes the next slot at once (one atomic per wave
+// for all idle lanes).  Per tracklet the sequence of filter operations is
+// exactly that of build_tracklet.
+enum { kIdle = 0, kOut = 1, kIn = 2, kDone = 3, kExhausted = 4 };
+
+__global__ __launch_bounds__(256) void k_tracklets_refill(Inputs in, Span sp, int R, const float* __restrict__ row_x,
+                                                          Consts c, Workspace ws, const int64_t* toff, int64_t first,
+                                                          int64_t cap, TrackletOut out, int nparts) {
+  const int64_t lo = max(toff[sp.s0], first);
+  const int64_t hi = min(toff[sp.s1], first + cap);
+  const int lane = threadIdx.x & 63;
+  Work w = {0, 0, 0, 0};
+  const Parts P = make_parts(lo, hi, nparts);
+  int kpart = 0;
+  int phase = kIdle;
+  int64_t o = 0, a = 0;
+  int s = 0, r0 = 0, r = 0, lastr = 0, first_row = 0, nh = 0, fl = 0, miss = 0;
+  int32_t h = -1, h0 = 0;
+  ChainHit nx = {0.0f, 0.0f, -1, 0};
+  Trk st, keep;  // keep: state at the last outward update, then the inward snapshot (the output)
+  while (true) {
+    // ---- idle lanes take the next slots
+    unsigned long long need = __ballot(phase == kIdle);
+    bool fresh = false;
+    while (need && kpart < P.nparts) {
+      const int part = (P.home + kpart) % P.nparts;
+      const int64_t plo = P.lo + (int64_t)part * P.len;
+      const int64_t phi = min(P.hi, plo + P.len);
+      const int n = __popcll(need);
+      unsigned long long base = 0;
+      if (lane == 0) base = atomicAdd(&ws.counters[kCtrWork + part], (unsigned long long)n);
+      base = __shfl(base, 0);
+      const int64_t s0 = plo + (int64_t)base;
+      if (phase == kIdle) {
+        const int64_t slot = s0 + __popcll(need & ((1ull << lane) - 1ull));
+        if (slot < phi) {
+          fresh = true;
+          o = slot - first;
+          s = sector_of(toff, sp.s0, sp.s1, slot);
+          a = in.hit_offset[s];
+          const int64_t gi = ws.start_glob[slot];
+          h0 = (int32_t)(gi - a);
+          r0 = in.row[gi];
+          const ChainHit c0 = ws.chain[gi];
+          const int32_t h1 = c0.up;
+          nx = ws.chain[a + h1];
+          nh = 1;
+          first_row = r0;
+          lastr = r0;
+          fl = 0;
+          miss = 0;
+          const int ei = init_track(st, row_x[r0], c0.y, c0.z, row_x[r0 + 1], nx.y, nx.z, c);
+          keep = st;
+          if (ei != kStepOk) {
+            fl |= stop_flag(ei);
+            phase = kDone;
+          } else {
+            h = h1;
+            r = r0;
+            phase = kOut;
+          }
+        }
+      }
+      if (s0 + n >= phi) ++kpart;
+      need = __ballot(phase == kIdle);
+    }
+    if (kpart >= P.nparts && phase == kIdle) phase = kExhausted;
+    // the wave clears the hit-per-row records of the new tracklets together
+    unsigned long long nw = __ballot(fresh);
+    if (nw) {
+      while (nw) {
+        const int L = __ffsll((long long)nw) - 1;
+        nw &= nw - 1ull;
+        const int64_t oL = __shfl(o, L);
+        int32_t* rec = out.row_hit + oL * R;
+        for (int k = lane; k < R; k += 64) rec[k] = -1;
+      }
+      __threadfence_block();
+    }
+    if (__ballot(phase != kExhausted) == 0ull) break;
+
+    // ---- one row step for lanes in a pass
+    if (phase == kOut || phase == kIn) {
+      const bool out_pass = phase == kOut;
+      const int rn = out_pass ? r + 1 : r - 1;
+      bool end_pass = out_pass ? rn >= R : rn < 0;
+      if (!end_pass) {
+        const bool search = out_pass ? h < 0 : rn < r0;
+        RowHdr hd;
+        if (search) hd = ws.hdr[(int64_t)s * R + rn];  // issued before the transport arithmetic
+        ++w.n_prop;
+        const int e = propagate(st, row_x[rn], c);
+        if (e) {
+          fl |= stop_flag(e);
+          end_pass = true;
+        } else {
+          r = rn;
+          Pick j = {-1, 0.0f, 0.0f};
+          if (out_pass && h >= 0) {
+            j.idx = h; j.y = nx.y; j.z = nx.z;
+          } else if (!out_pass && r == r0) {
+            keep = st;
+          }
+          if (search) j = closest(st, grid_of(hd, ws), c, w);
+          if (j.idx >= 0) {
+            Trk u = st;
+            ++w.n_upd;
+            if (update(u, j.y, j.z, c)) {
+              fl |= 2;
+              end_pass = true;
+            } else {
+              st = u;
+              keep = st;
+              out.row_hit[o * R + r] = j.idx;
+              ++nh;
+              miss = 0;
+              if (out_pass) {
+                lastr = r;
+                if (h >= 0) {
+                  h = nx.up;
+                  if (h >= 0) nx = ws.chain[a + h];
+                }
+              } else {
+                first_row = r;
+              }
+            }
+          } else if (search && ++miss > c.max_miss) {
+            end_pass = true;
+          }
+        }
+      }
+      if (end_pass) {
+        if (out_pass) {
+          st = keep;
+          r = lastr;
+          miss = 0;
+          phase = kIn;
+        } else {
+          phase = kDone;
+        }
+      }
+    }
+
+    // ---- finished tracklets write their record
+    if (phase == kDone) {
+      store_state(keep, o, out);
+      out.row_hit[o * R + r0] = h0;
+      if (nh >= c.min_hits) fl |= 1;
+      if (!spd_ok(keep)) fl |= 8;
+      out.start_row[o] = r0;
+      out.first_row[o] = first_row;
+      out.last_row[o] = lastr;
+      out.n_hits[o] = nh;
+      out.flags[o] = fl;
+      phase = kIdle;
+    }
   }
+  flush_work(w, ws, lane);
 }
 
 // ------------------------------------------------- binary64-covariance refit
@@ -807,10 +1172,11 @@ hipError_t launch_reset(unsigned long long* counters, int n, hipStream_t st) {
 
 hipError_t launch_row_index(const Inputs& in, Span sp, int n_rows, const Workspace& ws, int block, hipStream_t st) {
   const int64_t n_items = (int64_t)(sp.s1 - sp.s0) * (n_rows + 1);
-  const int64_t total = n_items + (sp.h1 - sp.h0);
+  const int64_t item_blocks = blocks_for(n_items, block);
+  const int64_t total = item_blocks + blocks_for(sp.h1 - sp.h0, block);
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_row_index, dim3(blocks_for(total, block)), dim3(block), 0, st, in, sp, n_rows,
-                     ws.row_first, ws.counters, n_items);
+  hipLaunchKernelGGL(k_row_index, dim3((unsigned)total), dim3(block), 0, st, in, sp, n_rows, ws.row_first,
+                     ws.counters, n_items, item_blocks);
   return hipGetLastError();
 }
 
@@ -821,12 +1187,14 @@ hipError_t launch_grid(const Inputs& in, Span sp, int n_rows, float bin_hits, co
   return hipGetLastError();
 }
 
-hipError_t launch_neighbours(const Inputs& in, Span sp, int n_rows, const float* row_x, const Consts& c,
-                             const Workspace& ws, int32_t* up, int32_t* dn, int block, hipStream_t st) {
-  const int64_t n = sp.h1 - sp.h0;
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_neighbours, dim3(blocks_for(n, block)), dim3(block), 0, st, in, sp, n_rows, row_x, c, ws,
-                     up, dn);
+hipError_t launch_neighbours(const Inputs& in, Span sp, int n_rows, const float4* rowk, const Consts& c,
+                             const Workspace& ws, int32_t* up, int32_t* dn, int block, int rows, int lds_bytes,
+                             hipStream_t st) {
+  const int64_t chunks = (n_rows + rows - 1) / rows;
+  const int64_t items = (int64_t)(sp.s1 - sp.s0) * chunks;
+  if (sp.h1 - sp.h0 == 0 || items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_neighbours, dim3((unsigned)items), dim3(block), (size_t)lds_bytes, st, in, sp, n_rows, rowk,
+                     c, ws, up, dn, rows, lds_bytes);
   return hipGetLastError();
 }
 
@@ -856,10 +1224,14 @@ hipError_t launch_compact(const Inputs& in, Span sp, int64_t* toff, int32_t* sta
 }
 
 hipError_t launch_tracklets(const Inputs& in, Span sp, int n_rows, const float* row_x, const Consts& c,
-                            const Workspace& ws, const int32_t* up_c, const int64_t* toff, int64_t first,
-                            int64_t cap, const TrackletOut& out, int grid, int block, hipStream_t st) {
-  hipLaunchKernelGGL(k_tracklets, dim3(grid), dim3(block), 0, st, in, sp, n_rows, row_x, c, ws, up_c, toff, first,
-                     cap, out);
+                            const Workspace& ws, const int64_t* toff, int64_t first, int64_t cap,
+                            const TrackletOut& out, int grid, int block, int refill, int nparts, hipStream_t st) {
+  if (refill)
+    hipLaunchKernelGGL(k_tracklets_refill, dim3(grid), dim3(block), 0, st, in, sp, n_rows, row_x, c, ws, toff, first,
+                       cap, out, nparts);
+  else
+    hipLaunchKernelGGL(k_tracklets, dim3(grid), dim3(block), 0, st, in, sp, n_rows, row_x, c, ws, toff, first, cap,
+                       out, nparts);
   return hipGetLastError();
 }
 

@@ -128,8 +128,14 @@ def test_tuning_does_not_change_results():
     _torch()
     b = synth.batch_workload(seed=5, n_events=2, lo=200, hi=3000)
     _, _, _, n0, l0, t0 = check_batch(b, sectors=[0, 17, 40])
-    for tun in ({"bin_hits": 0.5, "nf_block": 64, "tc_block": 64, "tc_waves_per_cu": 1, "use_graph": 0},
-                {"bin_hits": 16.0, "nf_block": 128, "tc_block": 128, "tc_waves_per_cu": 32, "use_graph": 1}):
+    for tun in ({"bin_hits": 0.5, "nf_block": 64, "tc_block": 64, "tc_waves_per_cu": 1, "use_graph": 0,
+                 "tc_refill": 0, "nf_rows": 1, "nf_lds_kb": 0, "tc_xcd": 0},
+                {"bin_hits": 16.0, "nf_block": 128, "tc_block": 128, "tc_waves_per_cu": 32, "use_graph": 1,
+                 "tc_refill": 1, "nf_rows": 16, "nf_lds_kb": 64, "tc_xcd": 1},
+                {"bin_hits": 1.0, "nf_block": 256, "tc_block": 256, "tc_waves_per_cu": 3, "use_graph": 1,
+                 "tc_refill": 0, "nf_rows": 3, "nf_lds_kb": 8, "tc_xcd": 1},
+                {"bin_hits": 0.5, "nf_block": 64, "tc_block": 64, "tc_waves_per_cu": 2, "use_graph": 0,
+                 "tc_refill": 1, "nf_rows": 2, "nf_lds_kb": 32, "tc_xcd": 0}):
         _, _, out, st, n = run_gpu(b, tuning=tun)
         assert n == n0
         l1, t1 = out.links_numpy(), out.tracklets_numpy(n)
