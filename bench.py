@@ -82,6 +82,36 @@ def cpu_baseline(batch, target_hits, cores):
             "seconds": dt}
 
 
+def serving_leg(args, tuning, log):
+    """Poisson stream of events (multiplicities as in the batch workload) through
+    the continuous-batching server; latency from arrival to results in host
+    memory (H2D, the hot path and D2H included)."""
+    import synth
+    from paper_1712_09430_amd import serve
+    log(f"[bench] serving: {args.serve_events} events at {args.serve_rate:g} Hz")
+    pool = synth.event_pool(seed=2, n_events=64)
+    rng = np.random.default_rng(3)
+    order = rng.integers(0, len(pool), args.serve_events)
+    arrival = serve.poisson_arrivals(args.serve_events, args.serve_rate, seed=4)
+    src = serve.EventStream(pool, order, arrival, pool[0].row_x)
+    res = serve.serve(src, tuning=tuning, warmup_events=args.serve_warmup)
+    log(f"[bench] serving: p50 {res['p50_ms']:.3f} ms, p99 {res['p99_ms']:.3f} ms, {res['hits_per_s']:.4g} hits/s, "
+        f"{res['batches']} batches, {res['slots']} slots")
+    # the same stream with every event waiting from the start: the server's
+    # saturated throughput (H2D, hot path and D2H of overlapping batches)
+    sat = serve.serve(src, tuning=tuning, warmup_events=0, realtime=False)
+    log(f"[bench] serving saturated: {sat['hits_per_s']:.4g} hits/s, {sat['batches']} batches")
+    return {"p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"], "hits_per_s": res["hits_per_s"],
+            "events": res["n_events"], "warmup_events": args.serve_warmup, "rate_hz": args.serve_rate,
+            "batches": res["batches"], "mean_batch_events": res["mean_batch_events"], "slots": res["slots"],
+            "hbm_budget_gib": res["hbm_budget_bytes"] / 2**30,
+            "slot_footprint_gib": res["slot_footprint_bytes"] / 2**30,
+            "latency": "arrival to results in host memory (H2D + hot path + D2H)",
+            "saturated_hits_per_s": sat["hits_per_s"], "saturated_batches": sat["batches"],
+            "late_fetches": res["late_fetches"],
+            "mean_event_hits": float(src.ev_hits.mean())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +129,9 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="launch the chain directly (for counter runs)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="before the timed region, one device copy of this many MiB (calibrates HBM counters)")
+    ap.add_argument("--serve-events", type=int, default=2200, help="serving leg: events in the stream (0: skip)")
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-rate", type=float, default=1000.0, help="serving leg: Poisson arrival rate, Hz")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the hot path shards by event with no "
@@ -123,12 +156,10 @@ def main():
     tuning_src = "library defaults"
     if args.tuning == "auto":
         from paper_1712_09430_amd import autotune
-        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
-        if os.path.exists(autotune.DEFAULT_CACHE):
-            cache = json.load(open(autotune.DEFAULT_CACHE))
-            if cache.get("arch", "").split(":")[0] == arch:
-                tr.set_tuning(cache["tuning"])
-                tuning_src = "autotuner cache " + os.path.basename(autotune.DEFAULT_CACHE)
+        cached = autotune.cached_tuning()
+        if cached is not None:
+            tr.set_tuning(cached)
+            tuning_src = "autotuner cache " + os.path.basename(autotune.DEFAULT_CACHE)
     elif args.tuning != "default":
         tr.set_tuning(json.load(open(args.tuning)))
         tuning_src = args.tuning
@@ -208,6 +239,10 @@ def main():
                  "launches_per_step": 7 * hits.n_sectors + 1, "status": int(st), "n_tracklets": n2}
         log(f"[bench] plain: {pms:.3f} ms/step, {plain['hits_per_s']:.4g} hits/s")
 
+    serving = None
+    if args.serve_events > 0:
+        serving = serving_leg(args, tuning, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         cores = min(16, os.cpu_count() or 1)
@@ -223,7 +258,7 @@ def main():
                       "sectors, persistent tracklet kernel, hipGraph replay", "parallelism": "single GPU",
                       "tuning": tuning, "tuning_source": tuning_src},
            "plain": plain, "batched_over_plain": (value / plain["hits_per_s"]) if plain else None,
-           "stages_ms": stages, "roofline": {k: v for k, v in dominant.items() if k != "kernel"} |
+           "serving": serving, "stages_ms": stages, "roofline": {k: v for k, v in dominant.items() if k != "kernel"} |
            {"kernel": dominant["kernel"]}, "rooflines": {"k_tracklets": rl_tc, "k_neighbours": rl_nf},
            "cpu_baseline": cpu}
     print(json.dumps(res), flush=True)

@@ -106,7 +106,8 @@ typedef struct {
   float* x_ref;              /* device [cap]: x of the fitted state (x of first_row) */
   float* param;              /* device [cap][5]: y, z, sin phi, tan lambda, q/pT at x_ref */
   float* cov;                /* device [cap][15]: packed lower triangle over the same order */
-  int32_t* row_hit;          /* device [cap][n_rows]: hit (sector-local) picked in each row, or -1 */
+  int32_t* row_hit;          /* device [n_rows][cap]: entry r*cap + t is the hit (sector-local) that
+                                tracklet t picked in row r, or -1 */
   int32_t* start_row;        /* device [cap] */
   int32_t* first_row;        /* device [cap] */
   int32_t* last_row;         /* device [cap] */

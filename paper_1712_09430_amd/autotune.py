@@ -29,6 +29,19 @@ SPACE = {
 }
 
 
+def cached_tuning(arch=None, path=DEFAULT_CACHE):
+    """The autotuner's result for this device architecture (dict), or None."""
+    if not os.path.exists(path):
+        return None
+    if arch is None:
+        import torch
+        arch = torch.cuda.get_device_properties(0).gcnArchName
+    cache = json.load(open(path))
+    if cache.get("arch", "").split(":")[0] != arch.split(":")[0]:
+        return None
+    return cache["tuning"]
+
+
 def time_config(tracker, hits, out, tuning, reps=5):
     import torch
     tracker.set_tuning(tuning)

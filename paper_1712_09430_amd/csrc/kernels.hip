@@ -661,6 +661,14 @@ __device__ __forceinline__ void store_state(const Trk& t, int64_t o, const Track
 
 __device__ __forceinline__ int stop_flag(int e) { return e == kStepSinPhi ? 2 : 4; }
 
+// Hit-per-row list of one tracklet in the [row][slot] output layout (a
+// wave's consecutive slots write one row with one coalesced store).
+struct RowHits {
+  int32_t* p;
+  int64_t stride;
+  __device__ __forceinline__ int32_t& operator[](int r) const { return p[(int64_t)r * stride]; }
+};
+
 // Wave totals of the method-step counts (one atomic per wave and counter).
 __device__ __forceinline__ void flush_work(const Work& w, const Workspace& ws, int lane) {
   unsigned long long v[4] = {(unsigned long long)w.n_prop, (unsigned long long)w.n_upd,
@@ -725,7 +733,7 @@ struct Seed {
 // One tracklet: slot -> start hit -> seed chain -> following -> output.
 __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __restrict__ row_x, const Consts& c,
                                const Workspace& ws, const int64_t* toff, int64_t slot, int64_t o,
-                               const TrackletOut& out, Work& w) {
+                               const TrackletOut& out, int64_t stride, Work& w) {
   const int s = sector_of(toff, sp.s0, sp.s1, slot);
   const int64_t a = in.hit_offset[s];
   const int64_t gi = ws.start_glob[slot];
@@ -734,7 +742,7 @@ __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __
   const ChainHit c0 = ws.chain[gi];
   const int32_t h1 = c0.up;
   ChainHit nx = ws.chain[a + h1];  // next chain measurement
-  int32_t* rh = out.row_hit + o * R;
+  const RowHits rh = {out.row_hit + o, stride};
   for (int r = 0; r < R; ++r) rh[r] = -1;
   rh[r0] = h0;
   int fl = 0;
@@ -831,7 +839,7 @@ __global__ __launch_bounds__(256) void k_tracklets(Inputs in, Span sp, int R, co
     const int64_t slot0 = take_slots(P, k, ws.counters + kCtrWork, 64, lane, pend);
     if (slot0 < 0) break;
     const int64_t slot = slot0 + lane;
-    if (slot < pend) build_tracklet(in, sp, R, row_x, c, ws, toff, slot, slot - first, out, w);
+    if (slot < pend) build_tracklet(in, sp, R, row_x, c, ws, toff, slot, slot - first, out, cap, w);
   }
   flush_work(w, ws, lane);
 }
@@ -911,7 +919,7 @@ __global__ __launch_bounds__(256) void k_tracklets_refill(Inputs in, Span sp, in
         const int L = __ffsll((long long)nw) - 1;
         nw &= nw - 1ull;
         const int64_t oL = __shfl(o, L);
-        int32_t* rec = out.row_hit + oL * R;
+        const RowHits rec = {out.row_hit + oL, cap};
         for (int k = lane; k < R; k += 64) rec[k] = -1;
       }
       __threadfence_block();
@@ -950,7 +958,7 @@ __global__ __launch_bounds__(256) void k_tracklets_refill(Inputs in, Span sp, in
             } else {
               st = u;
               keep = st;
-              out.row_hit[o * R + r] = j.idx;
+              out.row_hit[(int64_t)r * cap + o] = j.idx;
               ++nh;
               miss = 0;
               if (out_pass) {
@@ -983,7 +991,7 @@ __global__ __launch_bounds__(256) void k_tracklets_refill(Inputs in, Span sp, in
     // ---- finished tracklets write their record
     if (phase == kDone) {
       store_state(keep, o, out);
-      out.row_hit[o * R + r0] = h0;
+      out.row_hit[(int64_t)r0 * cap + o] = h0;
       if (nh >= c.min_hits) fl |= 1;
       if (!spd_ok(keep)) fl |= 8;
       out.start_row[o] = r0;
@@ -1087,7 +1095,7 @@ __global__ __launch_bounds__(256) void k_refit64(Inputs in, Span sp, int R, cons
     if (!((c.precision == 1 && (fl & 8)) || c.precision == 2)) continue;
     const int s = sector_of(toff, sp.s0, sp.s1, slot);
     const int64_t a = in.hit_offset[s];
-    const int32_t* rh = out.row_hit + o * R;
+    const RowHits rh = {out.row_hit + o, cap};
     const int r0 = out.start_row[o];
     MTrk st = {};
     MTrk snap;

@@ -64,7 +64,7 @@ class DeviceOutput:
         self.x_ref = e(cap, torch.float32)
         self.param = e((cap, 5), torch.float32)
         self.cov = e((cap, 15), torch.float32)
-        self.row_hit = e((cap, n_rows), i32)
+        self.row_hit = e((n_rows, cap), i32)  # [row][slot]
         self.start_row, self.first_row, self.last_row = e(cap, i32), e(cap, i32), e(cap, i32)
         self.n_hits, self.flags = e(cap, i32), e(cap, i32)
         s = C.catpc_output()
@@ -77,7 +77,8 @@ class DeviceOutput:
     def tracklets_numpy(self, n):
         n = min(int(n), self.capacity)
         g = lambda t: t[:n].cpu().numpy()
-        return {"x_ref": g(self.x_ref), "param": g(self.param), "cov": g(self.cov), "row_hit": g(self.row_hit),
+        return {"x_ref": g(self.x_ref), "param": g(self.param), "cov": g(self.cov),
+                "row_hit": np.ascontiguousarray(self.row_hit[:, :n].cpu().numpy().T),
                 "start_row": g(self.start_row), "first_row": g(self.first_row), "last_row": g(self.last_row),
                 "n_hits": g(self.n_hits), "flags": g(self.flags)}
 

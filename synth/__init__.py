@@ -253,6 +253,17 @@ def multiplicities(seed, n_events, lo=20.0, hi=1.0e4):
     return [int(lib().synth_multiplicity(seed, e, lo, hi)) for e in range(n_events)]
 
 
+def event_pool(seed=2, n_events=64, lo=20.0, hi=1.0e4, **kw):
+    """n_events single-event Batches with the same multiplicity law as
+    batch_workload (for streams of arriving events)."""
+    mult = multiplicities(seed, n_events, lo, hi)
+    from concurrent.futures import ThreadPoolExecutor
+    work = lambda i: Batch([(i, 0, generate_event(seed, mult[i], i, sectors=(0, N_SECTORS), **kw))],
+                           bz=kw.get("bz", BZ))
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        return list(ex.map(work, range(n_events)))
+
+
 def batch_workload(seed=1, n_events=64, lo=20.0, hi=1.0e4, truth=False, first_event=0, **kw):
     """n_events events with multiplicity floor(exp(U(ln lo, ln hi))): 36 sectors
     each, from near-empty sectors to central-heavy-ion-like ones."""
