@@ -74,12 +74,12 @@ typedef struct {
   int32_t tc_block;      /* threads per workgroup of the tracklet kernel [256] */
   int32_t tc_waves_per_cu; /* resident waves per CU of the persistent tracklet kernel [20] */
   int32_t use_graph;     /* 1: replay the batched stage chain as a captured hipGraph [1] */
-  int32_t tc_refill;     /* 1: a lane takes the next tracklet as soon as its own is done;
-                            0: a wave takes 64 tracklets at a time [0] */
   int32_t nf_rows;       /* pad rows per neighbour-finder workgroup (row chunk) [4] */
   int32_t nf_lds_kb;     /* LDS budget (KiB) for staging a row chunk and its two neighbour rows [32] */
   int32_t tc_xcd;        /* 1: tracklet slots split into one contiguous part per die, each die starting on its
                             own part (L2 locality) [1] */
+  int32_t tc_occupancy;  /* resident waves per SIMD the tracklet kernel's registers are fitted for:
+                            0 (the compiler's own allocation), 5, 6 or 8 (may spill to scratch) [0] */
 } catpc_tuning;
 
 /* Input hits (device pointers). */
@@ -106,8 +106,9 @@ typedef struct {
   float* x_ref;              /* device [cap]: x of the fitted state (x of first_row) */
   float* param;              /* device [cap][5]: y, z, sin phi, tan lambda, q/pT at x_ref */
   float* cov;                /* device [cap][15]: packed lower triangle over the same order */
-  int32_t* row_hit;          /* device [n_rows][cap]: entry r*cap + t is the hit (sector-local) that
-                                tracklet t picked in row r, or -1 */
+  int32_t* row_hit;          /* device [cap][catpc_row_stride(n_rows)], 16-byte aligned: entry
+                                t*stride + r is the hit (sector-local) that tracklet t picked in row r,
+                                or -1 (also in the padding rows r >= n_rows) */
   int32_t* start_row;        /* device [cap] */
   int32_t* first_row;        /* device [cap] */
   int32_t* last_row;         /* device [cap] */
@@ -120,6 +121,10 @@ typedef struct catpc_ctx catpc_ctx;
 /* Defaults of the method parameters and of the tuning. */
 void catpc_default_params(catpc_params* p);
 void catpc_default_tuning(catpc_tuning* t);
+
+/* Row stride of the hit-per-row output: n_rows rounded up to a multiple of 8
+ * (each tracklet's record is written in aligned 32-byte chunks). */
+int32_t catpc_row_stride(int32_t n_rows);
 
 /* Device workspace bytes catpc_create allocates for these maximum sizes. */
 size_t catpc_workspace_bytes(int32_t n_rows, int64_t max_hits, int32_t max_sectors);

@@ -1,8 +1,8 @@
 """Autotuner for the launch shape of the batched chain.
 
-Coordinate search over the catpc_tuning fields (grid-bin occupancy, block
-sizes of the per-hit kernels and of the tracklet kernel, resident waves per CU
-of the persistent tracklet kernel), timing the replayed hipGraph with HIP
+A joint grid over the tracklet kernel's register fit, resident waves per CU
+then a coordinate search over the other catpc_tuning
+fields (grid-bin occupancy, block sizes, row chunks, LDS staging), timing the replayed hipGraph with HIP
 events on the caller's stream.  The result never changes the output (the
 kernels' results do not depend on these values); it is written to a JSON cache
 keyed by the device architecture, which bench.py and the serving loop read.
@@ -17,10 +17,15 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tuning_gfx950.json")
 
+# Searched jointly first: how many waves the tracklet kernel keeps resident
+# depends on its register fit.
+JOINT = {
+    "tc_occupancy": [0, 5, 6, 8],
+    "tc_waves_per_cu": [8, 12, 16, 20, 24, 32],
+}
+# Then one coordinate at a time.
 SPACE = {
-    "tc_refill": [0, 1],
     "tc_xcd": [0, 1],
-    "tc_waves_per_cu": [4, 8, 12, 16, 20, 24, 32],
     "tc_block": [64, 128, 256],
     "bin_hits": [0.5, 1.0, 2.0, 4.0, 8.0],
     "nf_rows": [1, 2, 4, 8, 16],
@@ -70,6 +75,19 @@ def tune(tracker, hits, out, passes=2, log=print):
     best_ms = time_config(tracker, hits, out, cur)
     log(f"[autotune] start {cur} {best_ms:.3f} ms")
     trials = []
+    base = dict(cur)
+    for occ in JOINT["tc_occupancy"]:
+        for waves in JOINT["tc_waves_per_cu"]:
+            if occ and waves < 4 * occ - 8:
+                continue  # fewer resident waves than the occupancy variant is for
+            cand = dict(base, tc_occupancy=occ, tc_waves_per_cu=waves)
+            if cand == cur:
+                continue
+            ms = time_config(tracker, hits, out, cand)
+            trials.append((cand, ms))
+            log(f"[autotune] occupancy={occ} waves/CU={waves}: {ms:.3f} ms")
+            if ms < best_ms * 0.99:
+                best_ms, cur = ms, cand
     for _ in range(passes):
         changed = False
         for field, values in SPACE.items():
@@ -104,6 +122,9 @@ def main():
     torch.cuda.set_stream(stream)
     hits = DeviceHits(batch.y, batch.z, batch.row, batch.hit_offset, "cuda:0")
     tr = Tracker(batch.row_x, hits.n_hits, hits.n_sectors)
+    start = cached_tuning()
+    if start is not None:  # continue from the last result
+        tr.set_tuning(start)
     out = tr.output(hits)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     best, ms, trials = tune(tr, hits, out, log=log)

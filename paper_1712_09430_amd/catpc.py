@@ -22,7 +22,7 @@ FLAG_VALID, FLAG_STOP_SINPHI, FLAG_STOP_ARC, FLAG_SPD_FAIL, FLAG_REFIT64 = 1, 2,
 N_STAGES = 8
 STAGES = ("row_index", "grid", "neighbours", "clean_start", "scan", "compact", "tracklets", "refit64")
 
-EXPORTS = ("catpc_stage_times", "catpc_work_counts", "catpc_default_params", "catpc_default_tuning", "catpc_workspace_bytes", "catpc_create", "catpc_destroy",
+EXPORTS = ("catpc_stage_times", "catpc_work_counts", "catpc_default_params", "catpc_default_tuning", "catpc_row_stride", "catpc_workspace_bytes", "catpc_create", "catpc_destroy",
            "catpc_set_params", "catpc_set_tuning", "catpc_get_tuning", "catpc_track_batch", "catpc_track_plain",
            "catpc_result", "catpc_fetch_tracklets", "catpc_fp32_probe", "catpc_last_error")
 
@@ -42,8 +42,9 @@ class catpc_params(ctypes.Structure):
 
 class catpc_tuning(ctypes.Structure):
     _fields_ = [("bin_hits", ctypes.c_float), ("nf_block", ctypes.c_int32), ("tc_block", ctypes.c_int32),
-                ("tc_waves_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("tc_refill", ctypes.c_int32),
-                ("nf_rows", ctypes.c_int32), ("nf_lds_kb", ctypes.c_int32), ("tc_xcd", ctypes.c_int32)]
+                ("tc_waves_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("nf_rows", ctypes.c_int32), ("nf_lds_kb", ctypes.c_int32), ("tc_xcd", ctypes.c_int32),
+                ("tc_occupancy", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -77,6 +78,8 @@ def lib():
         L.catpc_default_params.restype = None
         L.catpc_default_tuning.argtypes = [P(catpc_tuning)]
         L.catpc_default_tuning.restype = None
+        L.catpc_row_stride.argtypes = [ctypes.c_int32]
+        L.catpc_row_stride.restype = ctypes.c_int32
         L.catpc_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]
         L.catpc_workspace_bytes.restype = ctypes.c_size_t
         L.catpc_create.argtypes = [ctypes.c_int32, _vp, P(catpc_params), ctypes.c_int64, ctypes.c_int32, P(_vp)]
@@ -128,6 +131,10 @@ def catpc_default_tuning():
     t = catpc_tuning()
     lib().catpc_default_tuning(ctypes.byref(t))
     return t
+
+
+def catpc_row_stride(n_rows):
+    return int(lib().catpc_row_stride(n_rows))
 
 
 def catpc_workspace_bytes(n_rows, max_hits, max_sectors):

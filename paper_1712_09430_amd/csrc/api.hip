@@ -37,7 +37,8 @@ catpc_status hip_fail(hipError_t e, const char* what) {
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t row_first, hdr, bins, sorted, raw_up, raw_dn, mask, blk_cnt, blk_off, start_glob, chain, counters;
+  size_t row_first, hdr, bins, sorted, raw_up, raw_dn, mask, blk_cnt, blk_off, grp_off, start_glob, chain,
+      counters;
   size_t total;
 };
 
@@ -55,6 +56,7 @@ Layout plan(int32_t R, int64_t H, int32_t S) {
   L.mask = take(sizeof(uint64_t) * (nblk * (kHitsPerBlock / 64) + 8));
   L.blk_cnt = take(sizeof(int32_t) * (nblk + 8));
   L.blk_off = take(sizeof(int64_t) * (nblk + 8));
+  L.grp_off = take(sizeof(int64_t) * (nblk / 1024 + 8));
   L.start_glob = take(sizeof(int32_t) * (size_t)(H + 1));
   L.chain = take(sizeof(ChainHit) * (size_t)(H + 1));
   L.counters = take(sizeof(unsigned long long) * kNumCounters);
@@ -146,6 +148,8 @@ catpc_status check_io(const catpc_ctx* ctx, const catpc_input* in, const catpc_o
       (!out->x_ref || !out->param || !out->cov || !out->row_hit || !out->start_row || !out->first_row ||
        !out->last_row || !out->n_hits || !out->flags))
     return fail(CATPC_E_INVALID, "tracklet arrays are NULL");
+  if (out->tracklet_capacity > 0 && ((uintptr_t)out->row_hit & 15))
+    return fail(CATPC_E_INVALID, "row_hit is not 16-byte aligned");
   if (need_host_off) {
     const int64_t* h = in->hit_offset_host;
     if (!h) return fail(CATPC_E_INVALID, "hit_offset_host is required");
@@ -219,7 +223,8 @@ catpc_status enqueue_span(catpc_ctx* ctx, const catpc_input* in, const catpc_out
   if (out->tracklet_capacity > 0) {
     HIP_TRY(launch_tracklets(I, sp, ctx->n_rows, ctx->row_x, ctx->consts, ws, out->tracklet_offset, 0,
                              out->tracklet_capacity, tracklets_of(out), tc_grid(ctx, (sp.h1 - sp.h0) / 3 + 1),
-                             ctx->tuning.tc_block, ctx->tuning.tc_refill, ctx->tuning.tc_xcd ? kXcds : 1, st));
+                             ctx->tuning.tc_block, ctx->tuning.tc_xcd ? kXcds : 1,
+                             ctx->tuning.tc_occupancy, st));
   }
   HIP_TRY(mark(7));
   return CATPC_OK;
@@ -275,11 +280,13 @@ void catpc_default_tuning(catpc_tuning* t) {
   t->tc_block = 256;
   t->tc_waves_per_cu = 20;
   t->use_graph = 1;
-  t->tc_refill = 0;
   t->nf_rows = 4;
   t->nf_lds_kb = 32;
   t->tc_xcd = 1;
+  t->tc_occupancy = 0;
 }
+
+int32_t catpc_row_stride(int32_t n_rows) { return n_rows > 0 ? row_stride(n_rows) : 0; }
 
 size_t catpc_workspace_bytes(int32_t n_rows, int64_t max_hits, int32_t max_sectors) {
   if (n_rows < 3 || max_hits < 0 || max_sectors < 0) return 0;
@@ -350,6 +357,7 @@ catpc_status catpc_create(int32_t n_rows, const float* row_x, const catpc_params
       w.start_mask = (uint64_t*)(b + L.mask);
       w.blk_cnt = (int32_t*)(b + L.blk_cnt);
       w.blk_off = (int64_t*)(b + L.blk_off);
+      w.grp_off = (int64_t*)(b + L.grp_off);
       w.start_glob = (int32_t*)(b + L.start_glob);
       w.chain = (ChainHit*)(b + L.chain);
       w.counters = (unsigned long long*)(b + L.counters);
@@ -393,11 +401,12 @@ catpc_status catpc_set_tuning(catpc_ctx* ctx, const catpc_tuning* t) {
   if (t->tc_block < 64 || t->tc_block > 256 || t->tc_block % 64)
     return fail(CATPC_E_INVALID, "tc_block must be a multiple of 64 in [64, 256]");
   if (t->tc_waves_per_cu < 1 || t->tc_waves_per_cu > 32) return fail(CATPC_E_INVALID, "tc_waves_per_cu out of [1, 32]");
-  if (t->use_graph < 0 || t->use_graph > 1 || t->tc_refill < 0 || t->tc_refill > 1)
-    return fail(CATPC_E_INVALID, "use_graph and tc_refill must be 0 or 1");
+  if (t->use_graph < 0 || t->use_graph > 1) return fail(CATPC_E_INVALID, "use_graph must be 0 or 1");
   if (t->nf_rows < 1 || t->nf_rows > 32) return fail(CATPC_E_INVALID, "nf_rows out of [1, 32]");
   if (t->nf_lds_kb < 0 || t->nf_lds_kb > 64) return fail(CATPC_E_INVALID, "nf_lds_kb out of [0, 64]");
   if (t->tc_xcd < 0 || t->tc_xcd > 1) return fail(CATPC_E_INVALID, "tc_xcd must be 0 or 1");
+  if (t->tc_occupancy != 0 && t->tc_occupancy != 5 && t->tc_occupancy != 6 && t->tc_occupancy != 8)
+    return fail(CATPC_E_INVALID, "tc_occupancy must be 0, 5, 6 or 8");
   ctx->tuning = *t;
   return CATPC_OK;
 }
@@ -518,6 +527,7 @@ catpc_status catpc_fetch_tracklets(catpc_ctx* ctx, const catpc_input* in, int64_
   if (!out->x_ref || !out->param || !out->cov || !out->row_hit || !out->start_row || !out->first_row ||
       !out->last_row || !out->n_hits || !out->flags)
     return fail(CATPC_E_INVALID, "tracklet arrays are NULL");
+  if ((uintptr_t)out->row_hit & 15) return fail(CATPC_E_INVALID, "row_hit is not 16-byte aligned");
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(ctx->device));
   const Span sp{0, in->n_sectors, 0, in->n_hits};
@@ -527,7 +537,7 @@ catpc_status catpc_fetch_tracklets(catpc_ctx* ctx, const catpc_input* in, int64_
   HIP_TRY(launch_reset(ctx->ws.counters, kXcds, st));
   HIP_TRY(launch_tracklets(I, sp, ctx->n_rows, ctx->row_x, ctx->consts, ctx->ws, o.tracklet_offset, first,
                            o.tracklet_capacity, tracklets_of(&o), tc_grid(ctx), ctx->tuning.tc_block,
-                           ctx->tuning.tc_refill, ctx->tuning.tc_xcd ? kXcds : 1, st));
+                           ctx->tuning.tc_xcd ? kXcds : 1, ctx->tuning.tc_occupancy, st));
   return enqueue_refit(ctx, in, &o, sp, first, st);
 }
 

@@ -56,7 +56,8 @@ struct Workspace {
   int32_t* raw_dn;       // [H]
   uint64_t* start_mask;  // [H/64 + 8] start-hit bits per wave
   int32_t* blk_cnt;      // [H/256 + 8] start hits per block
-  int64_t* blk_off;      // [H/256 + 8] first slot of each block
+  int64_t* blk_off;      // [H/256 + 8] first slot of each block, relative to its group of 1024 blocks
+  int64_t* grp_off;      // [H/256/1024 + 8] first slot of each group of 1024 blocks
   int32_t* start_glob;   // [H] global hit index of each tracklet slot
   ChainHit* chain;       // [H] coordinates + cleaned up-link per hit (input order)
   unsigned long long* counters; // [kNumCounters], see kCtr*
@@ -93,6 +94,9 @@ struct TrackletOut {
   int32_t* flags;
 };
 
+// Row stride of the hit-per-row output (whole chunks of 8 rows).
+__host__ __device__ inline int row_stride(int R) { return (R + 7) & ~7; }
+
 constexpr int kHitsPerBlock = 256;  // per-hit kernels: block size of clean/start/compaction
 constexpr int kMaxBinsPerRow = 1024;
 constexpr float kBinMargin = 1.0e-2f;  // cm, widens bin ranges beyond rounding of window edges
@@ -111,7 +115,7 @@ hipError_t launch_compact(const Inputs& in, Span sp, int64_t* toff, int32_t* sta
                           hipStream_t st);
 hipError_t launch_tracklets(const Inputs& in, Span sp, int n_rows, const float* row_x, const Consts& c,
                             const Workspace& ws, const int64_t* toff, int64_t first, int64_t cap,
-                            const TrackletOut& out, int grid, int block, int refill, int nparts, hipStream_t st);
+                            const TrackletOut& out, int grid, int block, int nparts, int waves, hipStream_t st);
 hipError_t launch_refit64(const Inputs& in, Span sp, int n_rows, const float* row_x, const Consts& c,
                           const Workspace& ws, const int64_t* toff, int64_t first, int64_t cap,
                           const TrackletOut& out, int grid, hipStream_t st);

@@ -423,13 +423,47 @@ __global__ __launch_bounds__(kHitsPerBlock) void k_clean_start(Inputs in, Span s
 }
 
 // -------------------------------------------------------------------- scan
-__global__ __launch_bounds__(1024) void k_scan(Span sp, int64_t nblk, int64_t* toff, Workspace ws) {
+// Two levels: each workgroup scans 1024 consecutive block counts (block
+// offsets relative to the group), then one workgroup scans the group totals.
+// The compaction adds the two.
+constexpr int kScanGroup = 1024;
+
+__global__ __launch_bounds__(kScanGroup) void k_scan_local(int64_t nblk, Workspace ws) {
+  __shared__ int wsum[kScanGroup / 64];
+  const int64_t b = (int64_t)blockIdx.x * kScanGroup + threadIdx.x;
+  const int v = b < nblk ? ws.blk_cnt[b] : 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int incl = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(incl, o);
+    if (lane >= o) incl += u;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  if (wave == 0) {
+    int x = lane < kScanGroup / 64 ? wsum[lane] : 0;
+    for (int o = 1; o < kScanGroup / 64; o <<= 1) {
+      const int u = __shfl_up(x, o);
+      if (lane >= o) x += u;
+    }
+    if (lane < kScanGroup / 64) wsum[lane] = x;
+  }
+  __syncthreads();
+  // entry nblk (one past the last block) gets the group's full prefix
+  if (b <= nblk) ws.blk_off[b] = (wave ? wsum[wave - 1] : 0) + incl - v;
+  if (threadIdx.x == kScanGroup - 1) ws.grp_off[blockIdx.x] = wsum[kScanGroup / 64 - 1];
+}
+
+// In-place exclusive scan of the ng group totals (plus the span's base slot);
+// grp_off[ng] = end of the span's slots.  Also clears the tracklet kernel's
+// work counters.
+__global__ __launch_bounds__(1024) void k_scan_top(Span sp, int64_t ng, int64_t* toff, Workspace ws) {
   __shared__ int64_t part[1024];
   const int t = threadIdx.x;
-  const int64_t per = (nblk + 1023) / 1024;
-  const int64_t b0 = min(nblk, (int64_t)t * per), b1 = min(nblk, b0 + per);
+  const int64_t per = (ng + 1023) / 1024;
+  const int64_t g0 = min(ng, (int64_t)t * per), g1 = min(ng, g0 + per);
   int64_t sum = 0;
-  for (int64_t b = b0; b < b1; ++b) sum += ws.blk_cnt[b];
+  for (int64_t g = g0; g < g1; ++g) sum += ws.grp_off[g];
   part[t] = sum;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
@@ -440,15 +474,20 @@ __global__ __launch_bounds__(1024) void k_scan(Span sp, int64_t nblk, int64_t* t
   }
   const int64_t base = sp.s0 == 0 ? 0 : toff[sp.s0];
   int64_t run = base + part[t] - sum;
-  for (int64_t b = b0; b < b1; ++b) {
-    ws.blk_off[b] = run;
-    run += ws.blk_cnt[b];
+  for (int64_t g = g0; g < g1; ++g) {
+    const int64_t v = ws.grp_off[g];
+    ws.grp_off[g] = run;
+    run += v;
   }
-  if (t == 1023) ws.blk_off[nblk] = base + part[1023];
+  if (t == 1023) ws.grp_off[ng] = base + part[1023];
   if (t == 0) {
     if (sp.s0 == 0) toff[0] = 0;
     for (int k = 0; k < kXcds; ++k) ws.counters[kCtrWork + k] = 0ull;
   }
+}
+
+__device__ __forceinline__ int64_t block_slot(const Workspace& ws, int64_t b) {
+  return ws.grp_off[b / kScanGroup] + ws.blk_off[b];
 }
 
 // ----------------------------------------------------------------- compact
@@ -462,7 +501,7 @@ __global__ __launch_bounds__(kHitsPerBlock) void k_compact(Inputs in, Span sp, i
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const unsigned long long m = ws.start_mask[(int64_t)blockIdx.x * W + wave];
     if (i < sp.h1 && ((m >> lane) & 1ull)) {
-      int64_t pos = ws.blk_off[blockIdx.x];
+      int64_t pos = block_slot(ws, blockIdx.x);
       for (int w = 0; w < wave; ++w) pos += __popcll(ws.start_mask[(int64_t)blockIdx.x * W + w]);
       pos += __popcll(m & ((1ull << lane) - 1ull));
       start_hit[pos] = (int32_t)(i - in.hit_offset[s]);
@@ -473,7 +512,7 @@ __global__ __launch_bounds__(kHitsPerBlock) void k_compact(Inputs in, Span sp, i
     if (s <= sp.s1) {
       const int64_t j = in.hit_offset[s] - sp.h0;
       const int64_t b = j / kHitsPerBlock;
-      int64_t p = ws.blk_off[b];
+      int64_t p = block_slot(ws, b);
       for (int64_t w = b * W; w < j / 64; ++w) p += __popcll(ws.start_mask[w]);
       const int rem = (int)(j & 63);
       if (rem) p += __popcll(ws.start_mask[j / 64] & ((1ull << rem) - 1ull));
@@ -551,14 +590,17 @@ __device__ __forceinline__ int propagate(Trk& t, float x1, const Consts& c) {
 }
 
 // Kalman update with a cluster (my, mz): independent scalar updates of the
-// transverse (y, s, q) and longitudinal (z, l) blocks.
+// transverse (y, s, q) and longitudinal (z, l) blocks.  An update that would
+// take |sin phi| to 0.999 or beyond is rejected and leaves the state as it was.
 __device__ __forceinline__ int update(Trk& t, float my, float mz, const Consts& c) {
   const float ry = my - t.y;
   const float Sy = t.c00 + c.sy2;
   const float iy = 1.0f / Sy;
   const float k0 = t.c00 * iy, k1 = t.c10 * iy, k2 = t.c20 * iy;
+  const float s1 = t.s + k1 * ry;
+  if (!(fabsf(s1) < 0.999f)) return kStepSinPhi;
   t.y = t.y + k0 * ry;
-  t.s = t.s + k1 * ry;
+  t.s = s1;
   t.q = t.q + k2 * ry;
   const float c00 = t.c00, c10 = t.c10, c20 = t.c20;
   t.c00 = c00 - k0 * c00;
@@ -577,7 +619,7 @@ __device__ __forceinline__ int update(Trk& t, float my, float mz, const Consts& 
   t.d00 = d00 - g0 * d00;
   t.d10 = d10 - g1 * d00;
   t.d11 = t.d11 - g1 * d10;
-  return fabsf(t.s) < 0.999f ? kStepOk : kStepSinPhi;
+  return kStepOk;
 }
 
 __device__ __forceinline__ bool spd_ok(const Trk& t) {
@@ -661,13 +703,38 @@ __device__ __forceinline__ void store_state(const Trk& t, int64_t o, const Track
 
 __device__ __forceinline__ int stop_flag(int e) { return e == kStepSinPhi ? 2 : 4; }
 
-// Hit-per-row list of one tracklet in the [row][slot] output layout (a
-// wave's consecutive slots write one row with one coalesced store).
-struct RowHits {
-  int32_t* p;
-  int64_t stride;
-  __device__ __forceinline__ int32_t& operator[](int r) const { return p[(int64_t)r * stride]; }
+// Hit-per-row record of one tracklet ([slot][row stride], row stride a
+// multiple of 8): a lane collects the aligned chunk of 8 rows it is in (in
+// LDS, one int per row and thread) and stores it whole, two 16-byte stores,
+// when it moves on, so every record entry is written once and no cache line is
+// written back per single hit.
+struct RowChunk {
+  int32_t* v;  // entry m of this thread at v[m * blockDim]
+  int stride;
+  int c;       // chunk index (rows 8c .. 8c+7)
 };
+
+__device__ __forceinline__ void chunk_clear(RowChunk& k, int c) {
+  k.c = c;
+#pragma unroll
+  for (int m = 0; m < 8; ++m) k.v[m * k.stride] = -1;
+}
+
+__device__ __forceinline__ void chunk_set(const RowChunk& k, int r, int32_t idx) { k.v[(r & 7) * k.stride] = idx; }
+
+__device__ __forceinline__ void chunk_store(const RowChunk& k, int32_t* rec) {
+  const int32_t* v = k.v;
+  const int S = k.stride;
+  int4* q = reinterpret_cast<int4*>(rec + 8 * k.c);
+  q[0] = make_int4(v[0], v[S], v[2 * S], v[3 * S]);
+  q[1] = make_int4(v[4 * S], v[5 * S], v[6 * S], v[7 * S]);
+}
+
+__device__ __forceinline__ void chunk_store_none(int c, int32_t* rec) {
+  int4* q = reinterpret_cast<int4*>(rec + 8 * c);
+  q[0] = make_int4(-1, -1, -1, -1);
+  q[1] = make_int4(-1, -1, -1, -1);
+}
 
 // Wave totals of the method-step counts (one atomic per wave and counter).
 __device__ __forceinline__ void flush_work(const Work& w, const Workspace& ws, int lane) {
@@ -730,10 +797,12 @@ struct Seed {
   float y1, z1;
 };
 
+constexpr int kTcMaxBlock = 256;
+
 // One tracklet: slot -> start hit -> seed chain -> following -> output.
 __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __restrict__ row_x, const Consts& c,
                                const Workspace& ws, const int64_t* toff, int64_t slot, int64_t o,
-                               const TrackletOut& out, int64_t stride, Work& w) {
+                               const TrackletOut& out, int RS, int32_t* chunk_lds, Work& w) {
   const int s = sector_of(toff, sp.s0, sp.s1, slot);
   const int64_t a = in.hit_offset[s];
   const int64_t gi = ws.start_glob[slot];
@@ -742,18 +811,22 @@ __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __
   const ChainHit c0 = ws.chain[gi];
   const int32_t h1 = c0.up;
   ChainHit nx = ws.chain[a + h1];  // next chain measurement
-  const RowHits rh = {out.row_hit + o, stride};
-  for (int r = 0; r < R; ++r) rh[r] = -1;
-  rh[r0] = h0;
+  int32_t* rec = out.row_hit + o * RS;
+  const int k0 = r0 >> 3;  // chunk of the start row
+  RowChunk k = {chunk_lds + threadIdx.x, (int)blockDim.x, k0};
+  chunk_clear(k, k0);
+  chunk_set(k, r0, h0);
+  int k_lo = k0, k_hi = k0;  // chunks written
   int fl = 0;
   int nh = 1, first_row = r0, lastr = r0;
-  Trk st, snap;
+  Trk st, snap;  // running state; snap: the state the output takes
   const int ei = init_track(st, row_x[r0], c0.y, c0.z, row_x[r0 + 1], nx.y, nx.z, c);
   if (ei != kStepOk) {
     fl |= stop_flag(ei);
     snap = st;
+    chunk_store(k, rec);
   } else {
-    Trk last = st;
+    snap = st;  // outward: the state at the last update
     // seed chain (no gate), then outward following
     int32_t h = h1;
     int miss = 0;
@@ -763,6 +836,11 @@ __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __
       ++w.n_prop;
       const int e = propagate(st, row_x[r], c);
       if (e) { fl |= stop_flag(e); break; }
+      if ((r >> 3) != k.c) {
+        chunk_store(k, rec);
+        chunk_clear(k, r >> 3);
+        k_hi = r >> 3;
+      }
       Pick j;
       if (h >= 0) {
         j.idx = h; j.y = nx.y; j.z = nx.z;
@@ -770,13 +848,11 @@ __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __
         j = closest(st, grid_of(hd, ws), c, w);
       }
       if (j.idx >= 0) {
-        Trk u = st;
         ++w.n_upd;
-        if (update(u, j.y, j.z, c)) { fl |= 2; break; }
-        st = u;
-        last = st;
+        if (update(st, j.y, j.z, c)) { fl |= 2; break; }
+        snap = st;
         lastr = r;
-        rh[r] = j.idx;
+        chunk_set(k, r, j.idx);
         ++nh;
         miss = 0;
         if (h >= 0) {
@@ -787,10 +863,13 @@ __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __
         break;
       }
     }
-    // back to the start row without updates, then inward following
-    st = last;
-    snap = last;
+    chunk_store(k, rec);
+    // back to the start row without updates, then inward following; hits in
+    // the start row's chunk (already stored) are written singly, chunks below
+    // it are collected as outward
+    st = snap;  // inward: snap becomes the state at the innermost update
     miss = 0;
+    k.c = k0;
     for (int r = lastr - 1; r >= 0; --r) {
       RowHdr hd;
       if (r < r0) hd = ws.hdr[(int64_t)s * R + r];
@@ -799,14 +878,20 @@ __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __
       if (e) { fl |= stop_flag(e); break; }
       if (r > r0) continue;
       if (r == r0) { snap = st; continue; }
+      if ((r >> 3) != k.c) {
+        if (k.c < k0) chunk_store(k, rec);
+        chunk_clear(k, r >> 3);
+        k_lo = r >> 3;
+      }
       const Pick j = closest(st, grid_of(hd, ws), c, w);
       if (j.idx >= 0) {
-        Trk u = st;
         ++w.n_upd;
-        if (update(u, j.y, j.z, c)) { fl |= 2; break; }
-        st = u;
+        if (update(st, j.y, j.z, c)) { fl |= 2; break; }
         snap = st;
-        rh[r] = j.idx;
+        if (k.c == k0)
+          rec[r] = j.idx;
+        else
+          chunk_set(k, r, j.idx);
         ++nh;
         first_row = r;
         miss = 0;
@@ -814,7 +899,11 @@ __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __
         break;
       }
     }
+    if (k.c < k0) chunk_store(k, rec);
   }
+  // chunks the passes did not reach
+  for (int q = 0; q < k_lo; ++q) chunk_store_none(q, rec);
+  for (int q = k_hi + 1; q < RS / 8; ++q) chunk_store_none(q, rec);
   store_state(snap, o, out);
   if (nh >= c.min_hits) fl |= 1;
   if (!spd_ok(snap)) fl |= 8;
@@ -825,9 +914,13 @@ __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __
   out.flags[o] = fl;
 }
 
-__global__ __launch_bounds__(256) void k_tracklets(Inputs in, Span sp, int R, const float* __restrict__ row_x,
-                                                   Consts c, Workspace ws, const int64_t* toff, int64_t first,
-                                                   int64_t cap, TrackletOut out, int nparts) {
+// kWaves > 0 asks the compiler to fit the kernel's registers for at least
+// kWaves resident waves per SIMD (spilling to scratch where needed).
+template <int kWaves>
+__global__ __launch_bounds__(kTcMaxBlock) __attribute__((amdgpu_waves_per_eu(kWaves > 0 ? kWaves : 1))) void
+k_tracklets(Inputs in, Span sp, int R, const float* __restrict__ row_x, Consts c, Workspace ws, const int64_t* toff,
+            int64_t first, int64_t cap, TrackletOut out, int nparts) {
+  __shared__ int32_t chunk_lds[8 * kTcMaxBlock];
   const int64_t lo = max(toff[sp.s0], first);
   const int64_t hi = min(toff[sp.s1], first + cap);
   const int lane = threadIdx.x & 63;
@@ -839,168 +932,7 @@ __global__ __launch_bounds__(256) void k_tracklets(Inputs in, Span sp, int R, co
     const int64_t slot0 = take_slots(P, k, ws.counters + kCtrWork, 64, lane, pend);
     if (slot0 < 0) break;
     const int64_t slot = slot0 + lane;
-    if (slot < pend) build_tracklet(in, sp, R, row_x, c, ws, toff, slot, slot - first, out, cap, w);
-  }
-  flush_work(w, ws, lane);
-}
-
-// Same tracklets, one row step per loop iteration for every lane, and a lane
-// whose tracklet is finished takes the next slot at once (one atomic per wave
-// for all idle lanes).  Per tracklet the sequence of filter operations is
-// exactly that of build_tracklet.
-enum { kIdle = 0, kOut = 1, kIn = 2, kDone = 3, kExhausted = 4 };
-
-__global__ __launch_bounds__(256) void k_tracklets_refill(Inputs in, Span sp, int R, const float* __restrict__ row_x,
-                                                          Consts c, Workspace ws, const int64_t* toff, int64_t first,
-                                                          int64_t cap, TrackletOut out, int nparts) {
-  const int64_t lo = max(toff[sp.s0], first);
-  const int64_t hi = min(toff[sp.s1], first + cap);
-  const int lane = threadIdx.x & 63;
-  Work w = {0, 0, 0, 0};
-  const Parts P = make_parts(lo, hi, nparts);
-  int kpart = 0;
-  int phase = kIdle;
-  int64_t o = 0, a = 0;
-  int s = 0, r0 = 0, r = 0, lastr = 0, first_row = 0, nh = 0, fl = 0, miss = 0;
-  int32_t h = -1, h0 = 0;
-  ChainHit nx = {0.0f, 0.0f, -1, 0};
-  Trk st, keep;  // keep: state at the last outward update, then the inward snapshot (the output)
-  while (true) {
-    // ---- idle lanes take the next slots
-    unsigned long long need = __ballot(phase == kIdle);
-    bool fresh = false;
-    while (need && kpart < P.nparts) {
-      const int part = (P.home + kpart) % P.nparts;
-      const int64_t plo = P.lo + (int64_t)part * P.len;
-      const int64_t phi = min(P.hi, plo + P.len);
-      const int n = __popcll(need);
-      unsigned long long base = 0;
-      if (lane == 0) base = atomicAdd(&ws.counters[kCtrWork + part], (unsigned long long)n);
-      base = __shfl(base, 0);
-      const int64_t s0 = plo + (int64_t)base;
-      if (phase == kIdle) {
-        const int64_t slot = s0 + __popcll(need & ((1ull << lane) - 1ull));
-        if (slot < phi) {
-          fresh = true;
-          o = slot - first;
-          s = sector_of(toff, sp.s0, sp.s1, slot);
-          a = in.hit_offset[s];
-          const int64_t gi = ws.start_glob[slot];
-          h0 = (int32_t)(gi - a);
-          r0 = in.row[gi];
-          const ChainHit c0 = ws.chain[gi];
-          const int32_t h1 = c0.up;
-          nx = ws.chain[a + h1];
-          nh = 1;
-          first_row = r0;
-          lastr = r0;
-          fl = 0;
-          miss = 0;
-          const int ei = init_track(st, row_x[r0], c0.y, c0.z, row_x[r0 + 1], nx.y, nx.z, c);
-          keep = st;
-          if (ei != kStepOk) {
-            fl |= stop_flag(ei);
-            phase = kDone;
-          } else {
-            h = h1;
-            r = r0;
-            phase = kOut;
-          }
-        }
-      }
-      if (s0 + n >= phi) ++kpart;
-      need = __ballot(phase == kIdle);
-    }
-    if (kpart >= P.nparts && phase == kIdle) phase = kExhausted;
-    // the wave clears the hit-per-row records of the new tracklets together
-    unsigned long long nw = __ballot(fresh);
-    if (nw) {
-      while (nw) {
-        const int L = __ffsll((long long)nw) - 1;
-        nw &= nw - 1ull;
-        const int64_t oL = __shfl(o, L);
-        const RowHits rec = {out.row_hit + oL, cap};
-        for (int k = lane; k < R; k += 64) rec[k] = -1;
-      }
-      __threadfence_block();
-    }
-    if (__ballot(phase != kExhausted) == 0ull) break;
-
-    // ---- one row step for lanes in a pass
-    if (phase == kOut || phase == kIn) {
-      const bool out_pass = phase == kOut;
-      const int rn = out_pass ? r + 1 : r - 1;
-      bool end_pass = out_pass ? rn >= R : rn < 0;
-      if (!end_pass) {
-        const bool search = out_pass ? h < 0 : rn < r0;
-        RowHdr hd;
-        if (search) hd = ws.hdr[(int64_t)s * R + rn];  // issued before the transport arithmetic
-        ++w.n_prop;
-        const int e = propagate(st, row_x[rn], c);
-        if (e) {
-          fl |= stop_flag(e);
-          end_pass = true;
-        } else {
-          r = rn;
-          Pick j = {-1, 0.0f, 0.0f};
-          if (out_pass && h >= 0) {
-            j.idx = h; j.y = nx.y; j.z = nx.z;
-          } else if (!out_pass && r == r0) {
-            keep = st;
-          }
-          if (search) j = closest(st, grid_of(hd, ws), c, w);
-          if (j.idx >= 0) {
-            Trk u = st;
-            ++w.n_upd;
-            if (update(u, j.y, j.z, c)) {
-              fl |= 2;
-              end_pass = true;
-            } else {
-              st = u;
-              keep = st;
-              out.row_hit[(int64_t)r * cap + o] = j.idx;
-              ++nh;
-              miss = 0;
-              if (out_pass) {
-                lastr = r;
-                if (h >= 0) {
-                  h = nx.up;
-                  if (h >= 0) nx = ws.chain[a + h];
-                }
-              } else {
-                first_row = r;
-              }
-            }
-          } else if (search && ++miss > c.max_miss) {
-            end_pass = true;
-          }
-        }
-      }
-      if (end_pass) {
-        if (out_pass) {
-          st = keep;
-          r = lastr;
-          miss = 0;
-          phase = kIn;
-        } else {
-          phase = kDone;
-        }
-      }
-    }
-
-    // ---- finished tracklets write their record
-    if (phase == kDone) {
-      store_state(keep, o, out);
-      out.row_hit[(int64_t)r0 * cap + o] = h0;
-      if (nh >= c.min_hits) fl |= 1;
-      if (!spd_ok(keep)) fl |= 8;
-      out.start_row[o] = r0;
-      out.first_row[o] = first_row;
-      out.last_row[o] = lastr;
-      out.n_hits[o] = nh;
-      out.flags[o] = fl;
-      phase = kIdle;
-    }
+    if (slot < pend) build_tracklet(in, sp, R, row_x, c, ws, toff, slot, slot - first, out, row_stride(R), chunk_lds, w);
   }
   flush_work(w, ws, lane);
 }
@@ -1095,7 +1027,7 @@ __global__ __launch_bounds__(256) void k_refit64(Inputs in, Span sp, int R, cons
     if (!((c.precision == 1 && (fl & 8)) || c.precision == 2)) continue;
     const int s = sector_of(toff, sp.s0, sp.s1, slot);
     const int64_t a = in.hit_offset[s];
-    const RowHits rh = {out.row_hit + o, cap};
+    const int32_t* rh = out.row_hit + o * row_stride(R);
     const int r0 = out.start_row[o];
     MTrk st = {};
     MTrk snap;
@@ -1217,7 +1149,9 @@ hipError_t launch_clean_start(const Inputs& in, Span sp, const int32_t* up, cons
 
 hipError_t launch_scan(Span sp, int64_t* toff, const Workspace& ws, hipStream_t st) {
   const int64_t nblk = (sp.h1 - sp.h0 + kHitsPerBlock - 1) / kHitsPerBlock;
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, sp, nblk, toff, ws);
+  const int64_t ng = nblk / kScanGroup + 1;  // covers entries [0, nblk]
+  hipLaunchKernelGGL(k_scan_local, dim3((unsigned)ng), dim3(kScanGroup), 0, st, nblk, ws);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, sp, ng, toff, ws);
   return hipGetLastError();
 }
 
@@ -1233,13 +1167,17 @@ hipError_t launch_compact(const Inputs& in, Span sp, int64_t* toff, int32_t* sta
 
 hipError_t launch_tracklets(const Inputs& in, Span sp, int n_rows, const float* row_x, const Consts& c,
                             const Workspace& ws, const int64_t* toff, int64_t first, int64_t cap,
-                            const TrackletOut& out, int grid, int block, int refill, int nparts, hipStream_t st) {
-  if (refill)
-    hipLaunchKernelGGL(k_tracklets_refill, dim3(grid), dim3(block), 0, st, in, sp, n_rows, row_x, c, ws, toff, first,
-                       cap, out, nparts);
-  else
-    hipLaunchKernelGGL(k_tracklets, dim3(grid), dim3(block), 0, st, in, sp, n_rows, row_x, c, ws, toff, first, cap,
-                       out, nparts);
+                            const TrackletOut& out, int grid, int block, int nparts, int waves, hipStream_t st) {
+#define CATPC_TC(K)                                                                                          \
+  hipLaunchKernelGGL(k_tracklets<K>, dim3(grid), dim3(block), 0, st, in, sp, n_rows, row_x, c, ws, toff, first, cap, \
+                     out, nparts)
+  switch (waves) {
+    case 5: CATPC_TC(5); break;
+    case 6: CATPC_TC(6); break;
+    case 8: CATPC_TC(8); break;
+    default: CATPC_TC(0); break;
+  }
+#undef CATPC_TC
   return hipGetLastError();
 }
 

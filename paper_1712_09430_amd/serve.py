@@ -33,7 +33,7 @@ from .tracker import Tracker, _ptr
 TRACKLET_FIELDS = (("x_ref", np.float32, ()), ("param", np.float32, (5,)), ("cov", np.float32, (15,)),
                    ("start_row", np.int32, ()), ("first_row", np.int32, ()), ("last_row", np.int32, ()),
                    ("n_hits", np.int32, ()), ("flags", np.int32, ()))
-BYTES_PER_TRACKLET = 4 * (1 + 5 + 15 + 5)  # plus 4 * n_rows for the hit-per-row list
+BYTES_PER_TRACKLET = 4 * (1 + 5 + 15 + 5)  # plus 4 * row stride for the hit-per-row record
 
 
 class EventStream:
@@ -90,7 +90,7 @@ class Slot:
         pin = lambda shape, dt: torch.empty(shape, dtype=dt, pin_memory=True)
         self.h_toff = pin(max_sectors + 1, torch.int64)
         self.h_trk = {f: pin((self.est,) + sh, getattr(torch, np.dtype(dt).name)) for f, dt, sh in TRACKLET_FIELDS}
-        self.h_rows = pin((self.n_rows * self.est,), torch.int32) if keep_rows else None
+        self.h_rows = pin((self.est, self.out.row_stride), torch.int32) if keep_rows else None
         self.done = torch.cuda.Event()
         self.busy = False
         self.events = None
@@ -100,7 +100,7 @@ class Slot:
     def footprint(self):
         ws = C.catpc_workspace_bytes(self.n_rows, self.max_hits, self.max_sectors)
         inputs = 12 * self.max_hits + 8 * (self.max_sectors + 1)
-        outputs = 12 * self.max_hits + 8 * (self.max_sectors + 1) + self.cap * (BYTES_PER_TRACKLET + 4 * self.n_rows)
+        outputs = 12 * self.max_hits + 8 * (self.max_sectors + 1) + self.cap * (BYTES_PER_TRACKLET + 4 * self.out.row_stride)
         return ws + inputs + outputs
 
     def submit(self, stream_src, e0, e1):
@@ -136,9 +136,7 @@ class Slot:
             for f, _, _ in TRACKLET_FIELDS:
                 self.h_trk[f][:est].copy_(getattr(self.out, f)[:est], non_blocking=True)
             if self.keep_rows:
-                # row_hit is [row][slot]: the first est slots of every row
-                self.h_rows[:self.n_rows * est].view(self.n_rows, est).copy_(self.out.row_hit[:, :est],
-                                                                             non_blocking=True)
+                self.h_rows[:est].copy_(self.out.row_hit[:est], non_blocking=True)
             self.done.record(self.stream)
         self.busy = True
         self.events = (e0, e1, ns, est)
@@ -152,14 +150,13 @@ class Slot:
             raise C.CatpcError(st, C.catpc_last_error())
         e0, e1, ns, est = self.events
         trk = {f: self.h_trk[f].numpy()[:min(n_trk, est)] for f, _, _ in TRACKLET_FIELDS}
-        rows = (self.h_rows.numpy()[:self.n_rows * est].reshape(self.n_rows, est)[:, :min(n_trk, est)].T
-                if self.keep_rows else None)
+        rows = self.h_rows.numpy()[:min(n_trk, est), :self.n_rows] if self.keep_rows else None
         self.late_fetches += int(n_trk > est)
         if n_trk > est:  # late fetch of the remainder
             with torch.cuda.stream(self.stream):
                 extra = {f: getattr(self.out, f)[est:n_trk].cpu().numpy() for f, _, _ in TRACKLET_FIELDS}
                 if self.keep_rows:
-                    rows = np.concatenate([rows, self.out.row_hit[:, est:n_trk].cpu().numpy().T])
+                    rows = np.concatenate([rows, self.out.row_hit[est:n_trk, :self.n_rows].cpu().numpy()])
             trk = {f: np.concatenate([trk[f], extra[f]]) for f in trk}
         self.busy = False
         res = None

@@ -64,7 +64,8 @@ class DeviceOutput:
         self.x_ref = e(cap, torch.float32)
         self.param = e((cap, 5), torch.float32)
         self.cov = e((cap, 15), torch.float32)
-        self.row_hit = e((n_rows, cap), i32)  # [row][slot]
+        self.row_stride = C.catpc_row_stride(n_rows)
+        self.row_hit = e((cap, self.row_stride), i32)  # [slot][row stride]
         self.start_row, self.first_row, self.last_row = e(cap, i32), e(cap, i32), e(cap, i32)
         self.n_hits, self.flags = e(cap, i32), e(cap, i32)
         s = C.catpc_output()
@@ -78,7 +79,7 @@ class DeviceOutput:
         n = min(int(n), self.capacity)
         g = lambda t: t[:n].cpu().numpy()
         return {"x_ref": g(self.x_ref), "param": g(self.param), "cov": g(self.cov),
-                "row_hit": np.ascontiguousarray(self.row_hit[:, :n].cpu().numpy().T),
+                "row_hit": np.ascontiguousarray(self.row_hit[:n, :self.n_rows].cpu().numpy()),
                 "start_row": g(self.start_row), "first_row": g(self.first_row), "last_row": g(self.last_row),
                 "n_hits": g(self.n_hits), "flags": g(self.flags)}
 

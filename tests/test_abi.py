@@ -65,3 +65,8 @@ def test_host_validation(lib):
     assert lib.catpc_track_batch(None, None, None, None) == C.CATPC_E_INVALID
     assert lib.catpc_result(None, None, None) == C.CATPC_E_INVALID
     assert lib.catpc_fp32_probe(7, None, None, None, 1, None) == C.CATPC_E_INVALID
+
+
+def test_row_stride(lib):
+    assert [C.catpc_row_stride(n) for n in (1, 7, 8, 9, 159, 160)] == [8, 8, 8, 16, 160, 160]
+    assert C.catpc_row_stride(0) == 0

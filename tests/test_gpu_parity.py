@@ -129,13 +129,13 @@ def test_tuning_does_not_change_results():
     b = synth.batch_workload(seed=5, n_events=2, lo=200, hi=3000)
     _, _, _, n0, l0, t0 = check_batch(b, sectors=[0, 17, 40])
     for tun in ({"bin_hits": 0.5, "nf_block": 64, "tc_block": 64, "tc_waves_per_cu": 1, "use_graph": 0,
-                 "tc_refill": 0, "nf_rows": 1, "nf_lds_kb": 0, "tc_xcd": 0},
+                 "nf_rows": 1, "nf_lds_kb": 0, "tc_xcd": 0, "tc_occupancy": 8},
                 {"bin_hits": 16.0, "nf_block": 128, "tc_block": 128, "tc_waves_per_cu": 32, "use_graph": 1,
-                 "tc_refill": 1, "nf_rows": 16, "nf_lds_kb": 64, "tc_xcd": 1},
+                 "nf_rows": 16, "nf_lds_kb": 64, "tc_xcd": 1, "tc_occupancy": 8},
                 {"bin_hits": 1.0, "nf_block": 256, "tc_block": 256, "tc_waves_per_cu": 3, "use_graph": 1,
-                 "tc_refill": 0, "nf_rows": 3, "nf_lds_kb": 8, "tc_xcd": 1},
+                 "nf_rows": 3, "nf_lds_kb": 8, "tc_xcd": 1, "tc_occupancy": 6},
                 {"bin_hits": 0.5, "nf_block": 64, "tc_block": 64, "tc_waves_per_cu": 2, "use_graph": 0,
-                 "tc_refill": 1, "nf_rows": 2, "nf_lds_kb": 32, "tc_xcd": 0}):
+                 "nf_rows": 2, "nf_lds_kb": 32, "tc_xcd": 0, "tc_occupancy": 6}):
         _, _, out, st, n = run_gpu(b, tuning=tun)
         assert n == n0
         l1, t1 = out.links_numpy(), out.tracklets_numpy(n)
@@ -259,3 +259,8 @@ def test_invariants_and_one_hypothesis_per_seed():
         ok = u >= 0
         assert np.all(row[u[ok]] == row[ok] + 1)
         assert len(np.unique(u[ok])) == ok.sum()  # at most one incoming link per hit
+    # the hit-per-row record is written in whole 8-row chunks: padding rows hold -1
+    rs = C.catpc_row_stride(len(b.row_x))
+    assert rs % 8 == 0 and rs >= len(b.row_x) and out.row_hit.shape[1] == rs
+    pad = out.row_hit[:n, len(b.row_x):].cpu().numpy()
+    assert pad.size == 0 or np.all(pad == -1)
