@@ -65,6 +65,7 @@ def lib():
             getattr(L, "oracle_update" + sfx).argtypes = [vp, real, real, vp]
             getattr(L, "oracle_spd" + sfx).argtypes = [vp]
         L.oracle_clean_links.argtypes = [i32, vp, vp, vp, vp, vp]
+        L.oracle_select.argtypes = [i32, i32, i32, vp, vp, vp, i32, vp, vp, vp, vp]
         L.oracle_refit_mixed.argtypes = [i32, vp, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
         for f in ("oracle_neighbours_f32", "oracle_neighbours_f64", "oracle_tracklets_f32",
                   "oracle_tracklets_f64", "oracle_refit_f32", "oracle_refit_f64", "oracle_clean_links",
@@ -110,6 +111,32 @@ def clean_links(up, dn):
     st = np.empty(n, np.uint8)
     lib().oracle_clean_links(n, up.ctypes.data, dn.ctypes.data, uc.ctypes.data, dc.ctypes.data, st.ctypes.data)
     return uc, dc, np.flatnonzero(st).astype(np.int32)
+
+
+def select(n_hits, row_hit, n_hits_trk, flags, min_hits=10):
+    """Tracklet selection of one sector (oracle/select.c).  Returns
+    (owned [n_trk], tracks: list of (tracklet index, kept hits by row))."""
+    rh = _c(row_hit, np.int32)
+    n_trk = rh.shape[0] if rh.ndim == 2 else 0
+    n_rows = rh.shape[1] if rh.ndim == 2 else 0
+    nt_ = _c(n_hits_trk, np.int32)
+    fl = _c(flags, np.int32)
+    owned = np.zeros(max(n_trk, 1), np.int32)
+    hits = np.zeros(max(int(n_trk) * max(n_rows, 1), 1), np.int32)
+    cnt = np.zeros(2, np.int32)
+    rc = lib().oracle_select(int(n_hits), n_rows, n_trk, rh.ctypes.data, nt_.ctypes.data, fl.ctypes.data,
+                             int(min_hits), owned.ctypes.data, hits.ctypes.data, cnt[0:].ctypes.data,
+                             cnt[1:].ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle_select failed ({rc})")
+    owned = owned[:n_trk]
+    tracks, pos = [], 0
+    for t in np.flatnonzero(owned):
+        k = int(owned[t])
+        tracks.append((int(t), hits[pos:pos + k].copy()))
+        pos += k
+    assert len(tracks) == cnt[0] and pos == cnt[1]
+    return owned, tracks
 
 
 def _trk_out(m, n_rows, real):

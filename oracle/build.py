@@ -21,7 +21,8 @@ def build(force: bool = True) -> str:
         units = [("tracker.c", ["-DORACLE_F32"], "tracker_f32.o"),
                  ("tracker.c", [], "tracker_f64.o"),
                  ("links.c", [], "links.o"),
-                 ("refit_mixed.c", [], "refit_mixed.o")]
+                 ("refit_mixed.c", [], "refit_mixed.o"),
+                 ("select.c", [], "select.o")]
         for src, defs, obj in units:
             o = os.path.join(tmp, obj)
             subprocess.run(["gcc", *CFLAGS, *defs, "-c", os.path.join(HERE, src), "-o", o], check=True)

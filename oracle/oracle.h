@@ -72,4 +72,13 @@ int32_t oracle_refit_mixed(int32_t n_rows, const float* row_x, int32_t n, const 
                            const int32_t* start_row, const oracle_params* p, float* x_ref,
                            float* param, float* cov, int32_t* spd_ok);
 
+/* Tracklet selection of one sector (select.c).  row_hit [n_trk][n_rows];
+ * outputs: owned[t] = hits tracklet t keeps if selected, else 0; track_hits =
+ * the selected tracklets' kept hits, tracklet by tracklet, rows ascending;
+ * n_tracks, n_track_hits = counts.  Returns 0, or <0 for a hit index out of
+ * range (-2) or no memory (-1). */
+int32_t oracle_select(int32_t n_hits, int32_t n_rows, int32_t n_trk, const int32_t* row_hit,
+                      const int32_t* trk_n_hits, const int32_t* flags, int32_t min_hits,
+                      int32_t* owned, int32_t* track_hits, int32_t* n_tracks, int32_t* n_track_hits);
+
 #endif
