@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 METRIC = "TPC hits/s (CA+tracklet fit) batched vs plain on 1 GPU; p99 event latency"
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
-# Algorithmic work per unit ("Measurement"):
+# Algorithmic work per unit (binary32 operations of the formulas, division and square root count 1):
 NF_BYTES_PER_HIT = 16.0        # y, z in (8 B) + up, down link out (8 B)
 FLOPS_PER_TRANSPORT = 75.0     # binary32 operations of one helix transport incl. covariance
 FLOPS_PER_UPDATE = 39.0        # two scalar Kalman updates
@@ -111,6 +111,109 @@ def cpu_baseline(batch, target_hits, cores):
             "seconds": dt}
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def peak_probes(torch, C, dev, stream, log):
+    """Achievable peaks on this GPU with the library's own probes: a 4 GiB
+    device copy (bytes read + written per second) and 8 independent FMA chains
+    per thread over 2^20 threads (binary32, non-packed)."""
+    n = 4 << 30
+    src = torch.empty(n // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sp = stream.cuda_stream
+    C.catpc_probe_copy(src.data_ptr(), dst.data_ptr(), n, sp)  # warm
+    reps = 5
+    e0.record(stream)
+    for _ in range(reps):
+        C.catpc_probe_copy(src.data_ptr(), dst.data_ptr(), n, sp)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    threads, iters = 1 << 20, 4096
+    out = torch.empty(threads, dtype=torch.float32, device=dev)
+    C.catpc_probe_fma(out.data_ptr(), threads, iters, sp)
+    e0.record(stream)
+    for _ in range(reps):
+        C.catpc_probe_fma(out.data_ptr(), threads, iters, sp)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fma_tflops = 16.0 * threads * iters * reps / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    log(f"[bench] probes: copy {copy_gbs:.0f} GB/s, FP32 FMA {fma_tflops:.1f} TFLOP/s")
+    return {"copy_gbs": copy_gbs, "fma_tflops": fma_tflops,
+            "copy": "4 GiB device copy, 16 B per lane, bytes read + written",
+            "fma": "2^20 threads x 4096 iterations x 8 independent binary32 FMA chains (non-packed)"}
+
+
+def precision_leg(torch, tuning, log):
+    """The precision form on the one-sector workload (200 tracks): tracklets
+    whose binary32 covariance fails the SPD check, tracklets refitted with a
+    binary64 covariance, and pulls of y, z, sin(phi) at x_ref against the
+    generator's true track position at the tracklet's innermost hit (signal
+    hits only), for the binary32 form and the precision form."""
+    import synth
+    from paper_1712_09430_amd import catpc as C
+    from paper_1712_09430_amd.tracker import DeviceHits, Tracker
+    b = synth.sector_workload(seed=1, n_tracks=200, truth=True)
+    hits = DeviceHits(b.y, b.z, b.row, b.hit_offset, "cuda:0")
+    rep = {"workload": "sector: one sector, 200 tracks, 159 pad rows, seed 1", "n_hits": hits.n_hits}
+    for prec in (0, 1):
+        p = C.catpc_default_params()
+        p.precision = prec
+        tr = Tracker(b.row_x, hits.n_hits, hits.n_sectors, params=p)
+        tr.set_tuning(dict(tuning, use_graph=0))
+        out = tr.output(hits)
+        tr.track(hits, out)
+        st, n = tr.result()
+        t = out.tracklets_numpy(n)
+        fl = t["flags"]
+        valid = (fl & C.FLAG_VALID) != 0
+        first_hit = t["row_hit"][np.arange(n), t["first_row"]]
+        sig = valid & (first_hit >= 0)
+        sig[sig] &= b.label[first_hit[sig]] >= 0
+        h = first_hit[sig]
+        pulls = {}
+        for name, k, ci, tk in (("y", 0, 0, "y_true"), ("z", 1, 2, "z_true"), ("sinphi", 2, 5, "sinphi_true")):
+            var = t["cov"][sig, ci].astype(np.float64)
+            ok = var > 0
+            pv = (t["param"][sig, k].astype(np.float64)[ok] - b.truth[tk][h][ok]) / np.sqrt(var[ok])
+            pulls[name] = {"mean": float(pv.mean()), "rms": float(np.sqrt((pv ** 2).mean())), "n": int(ok.sum())}
+        rep[f"precision_{prec}"] = {"tracklets": int(n), "valid": int(valid.sum()),
+                                    "spd_failures": int(((fl & C.FLAG_SPD_FAIL) != 0).sum()),
+                                    "refits": int(((fl & C.FLAG_REFIT64) != 0).sum()), "pulls": pulls}
+        tr.close()
+    log(f"[bench] precision: SPD failures {rep['precision_0']['spd_failures']}, "
+        f"refits {rep['precision_1']['refits']} of {rep['precision_1']['tracklets']} tracklets")
+    return rep
+
+
+def scheduling_leg(batch, tuning, hits_total, log):
+    """The paper's scheduling schemes for the per-sector form on this GPU
+    (Sec. 3.1: sectors over 8 queues; Sec. 3.2: several tracker instances by
+    event), beside the single persistent batched chain."""
+    from paper_1712_09430_amd.schedule import Queues
+    out = {}
+    for name, q, by, form, reps in (("plain_8_queues_by_sector", 8, "sector", "plain", 1),
+                                    ("plain_4_instances_by_event", 4, "event", "plain", 1),
+                                    ("batch_2_instances_by_event", 2, "event", "batch", 3),
+                                    ("batch_4_instances_by_event", 4, "event", "batch", 3)):
+        Q = Queues(batch, q, by=by, form=form, tuning=tuning)
+        ms = Q.time_ms(reps)
+        Q.close()
+        out[name] = {"ms_per_step": ms, "hits_per_s": hits_total / (ms * 1e-3)}
+        log(f"[bench] scheduling {name}: {ms:.2f} ms/step")
+    return out
+
+
 def serving_leg(args, tuning, log):
     """Poisson stream of events (multiplicities as in the batch workload) through
     the continuous-batching server; latency from arrival to results in host
@@ -144,12 +247,17 @@ def serving_leg(args, tuning, log):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch64")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--plain-steps", type=int, default=2)
-    ap.add_argument("--cpu-hits", type=float, default=6e6, help="oracle sample size for cpu_baseline")
+    ap.add_argument("--cpu-hits", type=float, default=3e7, help="oracle sample size for cpu_baseline (all threads)")
+    ap.add_argument("--cpu-hits-1", type=float, default=1.5e6, help="oracle sample size on one thread")
+    ap.add_argument("--cpu-hits-4", type=float, default=6e6, help="oracle sample size on four threads")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the copy and FMA peak probes")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision-form report")
+    ap.add_argument("--no-scheduling", action="store_true", help="skip the scheduling baselines")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", default="auto",
                     help="'auto' (the autotuner's cache for this architecture, if present), 'default', or a JSON "
@@ -158,13 +266,13 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="launch the chain directly (for counter runs)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="before the timed region, one device copy of this many MiB (calibrates HBM counters)")
-    ap.add_argument("--serve-events", type=int, default=2200, help="serving leg: events in the stream (0: skip)")
-    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-events", type=int, default=10500, help="serving leg: events in the stream (0: skip)")
+    ap.add_argument("--serve-warmup", type=int, default=500)
     ap.add_argument("--serve-rate", type=float, default=1000.0, help="serving leg: Poisson arrival rate, Hz")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; the hot path shards by event with no "
-                                   "exchange (see DESIGN.md), multi-GPU runs are not part of this build",
+        print(json.dumps({"error": "only the one-GPU form is implemented: the hot path would shard by event "
+                                   "with no exchange between GPUs, each GPU running this chain on its share",
                           "n_gpus": args.gpus}))
         raise SystemExit(2)
 
@@ -219,14 +327,18 @@ def main():
     # timed batched steps
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(args.steps):
+    ev[0].record(stream)
+    for k in range(args.steps):
         tr.track(hits, out)
+        ev[k + 1].record(stream)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = e0.elapsed_time(e1) / args.steps
+    step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
     st, n_trk = tr.result()
     if st != C.CATPC_OK:
         raise SystemExit(f"catpc status {st}: {C.catpc_last_error()}")
@@ -238,6 +350,22 @@ def main():
     work = tr.work_counts()
     stages = {name: float(v) for name, v in zip(C.STAGES, stage)}
     log("[bench] stages ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
+
+    # tracklet selection after the hot path (graph replay, HIP events on this stream)
+    tracks = tr.tracks_output(hits, out)
+    tr.track(hits, out)
+    tr.select(hits, out, tracks)
+    n_tracks, n_track_hits = tr.select_result()
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record(stream)
+    for _ in range(5):
+        tr.select(hits, out, tracks)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    sel = {"ms": s0.elapsed_time(s1) / 5, "tracks": n_tracks, "track_hits": n_track_hits,
+           "what": "tracklet selection of the batch's tracklets (hit ownership by weight, min_hits kept hits)"}
+    log(f"[bench] selection: {sel['ms']:.3f} ms, {n_tracks} tracks with {n_track_hits} hits")
+    del tracks
 
     flops = (work[0] * FLOPS_PER_TRANSPORT + work[1] * FLOPS_PER_UPDATE + work[3] * FLOPS_PER_SEARCH +
              work[2] * FLOPS_PER_CANDIDATE)
@@ -278,9 +406,28 @@ def main():
                  "launches_per_step": 8 * hits.n_sectors + 1, "status": int(st), "n_tracklets": n2}
         log(f"[bench] plain: {pms:.3f} ms/step, {plain['hits_per_s']:.4g} hits/s")
 
+    scheduling = None
+    if not args.no_scheduling:
+        scheduling = scheduling_leg(batch, tuning, hits.n_hits, log)
+        scheduling["plain_1_queue"] = {"ms_per_step": plain["ms_per_step"], "hits_per_s": plain["hits_per_s"]} \
+            if plain else None
+        scheduling["batch_1_instance"] = {"ms_per_step": ms_step, "hits_per_s": value}
+
     serving = None
     if args.serve_events > 0:
         serving = serving_leg(args, tuning, log)
+
+    peaks = None
+    if not args.no_peaks:
+        peaks = peak_probes(torch, C, dev, stream, log)
+        for rl in (rl_tc, rl_nf):
+            key = "fma_tflops" if rl["bound"] == "alu" else "copy_gbs"
+            rl["achievable_peak"] = peaks[key]
+            rl["frac_of_achievable"] = rl["achieved"] / peaks[key]
+
+    precision = None
+    if not args.no_precision:
+        precision = precision_leg(torch, tuning, log)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -288,9 +435,20 @@ def main():
         log(f"[bench] oracle on a sample, {cores} threads")
         cpu = cpu_baseline(batch, args.cpu_hits, cores)
         log(f"[bench] oracle: {cpu['value']:.4g} hits/s")
+        one = cpu_baseline(batch, args.cpu_hits_1, 1)
+        log(f"[bench] oracle, one thread: {one['value']:.4g} hits/s")
+        cpu["single_thread"] = {"value": one["value"], "sample": one["sample"]}
+        four = cpu_baseline(batch, args.cpu_hits_4, 4)
+        log(f"[bench] oracle, four threads: {four['value']:.4g} hits/s")
+        cpu["four_threads"] = {"value": four["value"], "sample": four["sample"]}
+        cpu["gpu_over_four_threads"] = value / four["value"]
+        cpu["paper_context"] = ("the paper quotes its GPU tracker at about 10x four CPU cores on its own Run-1 "
+                                "hardware (Sec. 1); context only, different hardware, code and data")
+        cpu["nproc"] = os.cpu_count()
+        cpu["cpu_model"] = cpu_model()
 
     res = {"metric": METRIC, "value": value, "unit": "hits/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+           "warmup": args.warmup, "ms_per_step": ms_step, "ms_per_step_median": float(np.median(step_ms)), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded helix events, no recorded data)",
            "config": {"workload": desc, "n_hits": hits.n_hits, "n_sectors": hits.n_sectors,
                       "n_tracklets": n_trk, "seed": args.seed, "form": "batched: fixed launch chain over all "
@@ -299,7 +457,7 @@ def main():
            "plain": plain, "batched_over_plain": (value / plain["hits_per_s"]) if plain else None,
            "serving": serving, "stages_ms": stages, "roofline": {k: v for k, v in dominant.items() if k != "kernel"} |
            {"kernel": dominant["kernel"]}, "rooflines": {"k_tracklets": rl_tc, "k_neighbours": rl_nf},
-           "cpu_baseline": cpu}
+           "selection": sel, "scheduling": scheduling, "achievable_peaks": peaks, "precision": precision, "cpu_baseline": cpu}
     print(json.dumps(res), flush=True)
 
 

@@ -80,6 +80,8 @@ typedef struct {
                             own part (L2 locality) [1] */
   int32_t tc_occupancy;  /* resident waves per SIMD the tracklet kernel's registers are fitted for:
                             0 (the compiler's own allocation), 5, 6 or 8 (may spill to scratch) [0] */
+  int32_t tc_sync;       /* 1: the lanes of a wave step through the pad rows together, reading the same row
+                            grids at the same time [0] */
 } catpc_tuning;
 
 /* Input hits (device pointers). */
@@ -91,6 +93,9 @@ typedef struct {
   const int64_t* hit_offset_host;/* host copy of hit_offset; required by catpc_track_plain, optional otherwise */
   int32_t n_sectors;
   int64_t n_hits;                /* == hit_offset[n_sectors] */
+  const float* x;                /* device [n_hits] or NULL: x of each hit (cm); every hit lies on its pad-row
+                                    plane, so the path uses row_x[row]; when given, x[i] == row_x[row[i]] is
+                                    checked and a difference reported by catpc_result as CATPC_E_INVALID */
 } catpc_input;
 
 /* Outputs (device pointers, caller-owned). */
@@ -116,6 +121,23 @@ typedef struct {
   int32_t* flags;            /* device [cap]: CATPC_FLAG_* */
 } catpc_output;
 
+/* Selected track segments (caller-owned device memory), written by
+ * catpc_select_tracklets.  Tracks of sector s are [track_offset[s],
+ * track_offset[s+1]), in tracklet order; the hits of track k are
+ * track_hits[track_hit_offset[k] .. + track_n_hits[k]), sector-local, rows
+ * ascending.  No hit is in two tracks, so hit_capacity = n_hits and
+ * track_capacity = the number of tracklets always suffice. */
+typedef struct {
+  int64_t* track_offset;     /* device [n_sectors+1] */
+  int32_t* track_tracklet;   /* device [track_capacity]: sector-local index of the tracklet the track comes from
+                                (its slot is tracklet_offset[s] + this) */
+  int32_t* track_n_hits;     /* device [track_capacity]: hits the track keeps */
+  int64_t* track_hit_offset; /* device [track_capacity]: first entry of its hits in track_hits */
+  int64_t track_capacity;
+  int32_t* track_hits;       /* device [hit_capacity] */
+  int64_t hit_capacity;
+} catpc_tracks;
+
 typedef struct catpc_ctx catpc_ctx;
 
 /* Defaults of the method parameters and of the tuning. */
@@ -130,9 +152,9 @@ int32_t catpc_row_stride(int32_t n_rows);
 size_t catpc_workspace_bytes(int32_t n_rows, int64_t max_hits, int32_t max_sectors);
 
 /* Create a tracker on the current HIP device.  row_x: host [n_rows], x of
- * each pad row (cm, ascending); max_hits / max_sectors bound every later
- * call.  Allocates the workspace once.  Returns CATPC_E_INVALID for bad sizes,
- * CATPC_E_HIP if allocation fails. */
+ * each pad row (cm, ascending), 3 <= n_rows <= 4096; max_hits / max_sectors
+ * bound every later call.  Allocates the workspace once.  Returns
+ * CATPC_E_INVALID for bad sizes, CATPC_E_HIP if allocation fails. */
 catpc_status catpc_create(int32_t n_rows, const float* row_x, const catpc_params* params, int64_t max_hits,
                           int32_t max_sectors, catpc_ctx** out);
 void catpc_destroy(catpc_ctx* ctx);
@@ -192,6 +214,35 @@ catpc_status catpc_work_counts(catpc_ctx* ctx, void* stream, int64_t* counts);
  * op 0 '+', 1 '-', 2 '*', 3 '/', 4 sqrt(a[i]); device pointers, n elements.
  * Used to check that the device rounds like the host. */
 catpc_status catpc_fp32_probe(int32_t op, const float* a, const float* b, float* out, int64_t n, void* stream);
+
+/* Tracklet selection (Sec. 2 item 2: of several seeds followed along the
+ * same track segment the best instance is kept and the others are removed;
+ * Sec. 3: it runs after the tracklet construction, many sectors per launch).
+ * Reads the tracklets of a finished track call (`trk`: tracklet_offset,
+ * flags, n_hits, row_hit) for the hits `in`.  Every hit goes to the heaviest
+ * valid tracklet that lists it (weight: hit count, then the smaller
+ * sector-local tracklet index); a tracklet that keeps at least min_hits of
+ * its hits becomes a track of those hits.  Deterministic: the result does not
+ * depend on the order of the device's atomics.  Asynchronous on `stream`;
+ * catpc_select_result reports the totals.  Returns CATPC_E_INVALID for
+ * missing or misaligned arrays. */
+catpc_status catpc_select_tracklets(catpc_ctx* ctx, const catpc_input* in, const catpc_output* trk,
+                                    const catpc_tracks* out, void* stream);
+
+/* Synchronise `stream` and report the last selection: the number of tracks
+ * and of their hits.  CATPC_E_CAPACITY if the output held fewer, or if the
+ * tracklet output held only part of the tracklets (then the selection covers
+ * only those); CATPC_E_INVALID if a tracklet record named a hit outside its
+ * sector; CATPC_E_STATE without a selection since the last track call. */
+catpc_status catpc_select_result(catpc_ctx* ctx, void* stream, int64_t* n_tracks, int64_t* n_track_hits);
+
+/* Achievable-peak probes (measurement only, no tracking): a device copy of
+ * n_bytes (a multiple of 16; 16-byte aligned device pointers), and in each of
+ * n_threads threads 8 independent chains of n_iter binary32 fused
+ * multiply-adds (16 * n_iter flops per thread; out[i] receives a sum so the
+ * work stays).  Asynchronous on `stream`; time them with events there. */
+catpc_status catpc_probe_copy(const void* src, void* dst, int64_t n_bytes, void* stream);
+catpc_status catpc_probe_fma(float* out, int64_t n_threads, int32_t n_iter, void* stream);
 
 /* Thread-local text of the last error. */
 const char* catpc_last_error(void);

@@ -20,6 +20,7 @@ DEFAULT_CACHE = os.path.join(HERE, "tuning_gfx950.json")
 # Searched jointly first: how many waves the tracklet kernel keeps resident
 # depends on its register fit.
 JOINT = {
+    "tc_sync": [0, 1],
     "tc_occupancy": [0, 5, 6, 8],
     "tc_waves_per_cu": [8, 12, 16, 20, 24, 32],
 }
@@ -76,18 +77,19 @@ def tune(tracker, hits, out, passes=2, log=print):
     log(f"[autotune] start {cur} {best_ms:.3f} ms")
     trials = []
     base = dict(cur)
-    for occ in JOINT["tc_occupancy"]:
-        for waves in JOINT["tc_waves_per_cu"]:
-            if occ and waves < 4 * occ - 8:
-                continue  # fewer resident waves than the occupancy variant is for
-            cand = dict(base, tc_occupancy=occ, tc_waves_per_cu=waves)
-            if cand == cur:
-                continue
-            ms = time_config(tracker, hits, out, cand)
-            trials.append((cand, ms))
-            log(f"[autotune] occupancy={occ} waves/CU={waves}: {ms:.3f} ms")
-            if ms < best_ms * 0.99:
-                best_ms, cur = ms, cand
+    for sync in JOINT["tc_sync"]:
+        for occ in JOINT["tc_occupancy"]:
+            for waves in JOINT["tc_waves_per_cu"]:
+                if occ and waves < 4 * occ - 8:
+                    continue  # fewer resident waves than the occupancy variant is for
+                cand = dict(base, tc_sync=sync, tc_occupancy=occ, tc_waves_per_cu=waves)
+                if cand == cur:
+                    continue
+                ms = time_config(tracker, hits, out, cand)
+                trials.append((cand, ms))
+                log(f"[autotune] sync={sync} occupancy={occ} waves/CU={waves}: {ms:.3f} ms")
+                if ms < best_ms * 0.99:
+                    best_ms, cur = ms, cand
     for _ in range(passes):
         changed = False
         for field, values in SPACE.items():

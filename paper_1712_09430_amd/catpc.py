@@ -24,7 +24,8 @@ STAGES = ("row_index", "grid", "neighbours", "clean_start", "scan", "compact", "
 
 EXPORTS = ("catpc_stage_times", "catpc_work_counts", "catpc_default_params", "catpc_default_tuning", "catpc_row_stride", "catpc_workspace_bytes", "catpc_create", "catpc_destroy",
            "catpc_set_params", "catpc_set_tuning", "catpc_get_tuning", "catpc_track_batch", "catpc_track_plain",
-           "catpc_result", "catpc_fetch_tracklets", "catpc_fp32_probe", "catpc_last_error")
+           "catpc_result", "catpc_fetch_tracklets", "catpc_select_tracklets", "catpc_select_result", "catpc_fp32_probe", "catpc_probe_copy", "catpc_probe_fma",
+           "catpc_last_error")
 
 
 class CatpcError(RuntimeError):
@@ -44,7 +45,7 @@ class catpc_tuning(ctypes.Structure):
     _fields_ = [("bin_hits", ctypes.c_float), ("nf_block", ctypes.c_int32), ("tc_block", ctypes.c_int32),
                 ("tc_waves_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("nf_rows", ctypes.c_int32), ("nf_lds_kb", ctypes.c_int32), ("tc_xcd", ctypes.c_int32),
-                ("tc_occupancy", ctypes.c_int32)]
+                ("tc_occupancy", ctypes.c_int32), ("tc_sync", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -52,7 +53,7 @@ _vp = ctypes.c_void_p
 
 class catpc_input(ctypes.Structure):
     _fields_ = [("y", _vp), ("z", _vp), ("row", _vp), ("hit_offset", _vp), ("hit_offset_host", _vp),
-                ("n_sectors", ctypes.c_int32), ("n_hits", ctypes.c_int64)]
+                ("n_sectors", ctypes.c_int32), ("n_hits", ctypes.c_int64), ("x", _vp)]
 
 
 class catpc_output(ctypes.Structure):
@@ -60,6 +61,11 @@ class catpc_output(ctypes.Structure):
                 ("tracklet_offset", _vp), ("tracklet_capacity", ctypes.c_int64), ("x_ref", _vp), ("param", _vp),
                 ("cov", _vp), ("row_hit", _vp), ("start_row", _vp), ("first_row", _vp), ("last_row", _vp),
                 ("n_hits", _vp), ("flags", _vp)]
+
+
+class catpc_tracks(ctypes.Structure):
+    _fields_ = [("track_offset", _vp), ("track_tracklet", _vp), ("track_n_hits", _vp), ("track_hit_offset", _vp),
+                ("track_capacity", ctypes.c_int64), ("track_hits", _vp), ("hit_capacity", ctypes.c_int64)]
 
 
 _lib = None
@@ -99,12 +105,20 @@ def lib():
         L.catpc_result.restype = st
         L.catpc_fetch_tracklets.argtypes = [_vp, P(catpc_input), ctypes.c_int64, P(catpc_output), _vp]
         L.catpc_fetch_tracklets.restype = st
+        L.catpc_select_tracklets.argtypes = [_vp, P(catpc_input), P(catpc_output), P(catpc_tracks), _vp]
+        L.catpc_select_tracklets.restype = st
+        L.catpc_select_result.argtypes = [_vp, _vp, P(ctypes.c_int64), P(ctypes.c_int64)]
+        L.catpc_select_result.restype = st
         L.catpc_stage_times.argtypes = [_vp, P(catpc_input), P(catpc_output), _vp, _vp]
         L.catpc_stage_times.restype = st
         L.catpc_work_counts.argtypes = [_vp, _vp, _vp]
         L.catpc_work_counts.restype = st
         L.catpc_fp32_probe.argtypes = [ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int64, _vp]
         L.catpc_fp32_probe.restype = st
+        L.catpc_probe_copy.argtypes = [_vp, _vp, ctypes.c_int64, _vp]
+        L.catpc_probe_copy.restype = st
+        L.catpc_probe_fma.argtypes = [_vp, ctypes.c_int64, ctypes.c_int32, _vp]
+        L.catpc_probe_fma.restype = st
         L.catpc_last_error.argtypes = []
         L.catpc_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -187,6 +201,18 @@ def catpc_fetch_tracklets(ctx, inp, first, out, stream):
     return _check(lib().catpc_fetch_tracklets(ctx, ctypes.byref(inp), int(first), ctypes.byref(out), stream))
 
 
+def catpc_select_tracklets(ctx, inp, trk, tracks, stream):
+    return _check(lib().catpc_select_tracklets(ctx, ctypes.byref(inp), ctypes.byref(trk), ctypes.byref(tracks),
+                                               stream))
+
+
+def catpc_select_result(ctx, stream):
+    """Synchronise; returns (n_tracks, n_track_hits) of the last selection."""
+    nt, nh = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().catpc_select_result(ctx, stream, ctypes.byref(nt), ctypes.byref(nh)))
+    return int(nt.value), int(nh.value)
+
+
 def catpc_stage_times(ctx, inp, out, stream):
     """Per-stage milliseconds (numpy float32[N_STAGES]) of one batched run."""
     ms = np.zeros(N_STAGES, np.float32)
@@ -203,3 +229,11 @@ def catpc_work_counts(ctx, stream):
 
 def catpc_fp32_probe(op, a, b, out, n, stream):
     return _check(lib().catpc_fp32_probe(int(op), a, b, out, int(n), stream))
+
+
+def catpc_probe_copy(src, dst, n_bytes, stream):
+    return _check(lib().catpc_probe_copy(src, dst, int(n_bytes), stream))
+
+
+def catpc_probe_fma(out, n_threads, n_iter, stream):
+    return _check(lib().catpc_probe_fma(out, int(n_threads), int(n_iter), stream))

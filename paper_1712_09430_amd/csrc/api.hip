@@ -38,7 +38,7 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
   size_t row_first, hdr, bins, sorted, raw_up, raw_dn, mask, blk_cnt, blk_off, grp_off, start_glob, chain,
-      counters;
+      owner, sel_cnt, sel_loc, sel_grp, counters;
   size_t total;
 };
 
@@ -59,6 +59,11 @@ Layout plan(int32_t R, int64_t H, int32_t S) {
   L.grp_off = take(sizeof(int64_t) * (nblk / 1024 + 8));
   L.start_glob = take(sizeof(int32_t) * (size_t)(H + 1));
   L.chain = take(sizeof(ChainHit) * (size_t)(H + 1));
+  const size_t slots = (size_t)(H / 3) + 2;  // tracklets <= H/3: seeds are disjoint chains of >= 3 hits
+  L.owner = take(sizeof(unsigned) * (size_t)(H + 1));
+  L.sel_cnt = take(sizeof(int32_t) * slots);
+  L.sel_loc = take(sizeof(int2) * slots);
+  L.sel_grp = take(sizeof(longlong2) * (slots / 1024 + 8));
   L.counters = take(sizeof(unsigned long long) * kNumCounters);
   L.total = o;
   return L;
@@ -71,6 +76,16 @@ struct GraphKey {
   catpc_params params;
   catpc_tuning tuning;
   bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
+};
+
+// Arguments of the last captured selection chain.
+struct SelKey {
+  catpc_input in;
+  catpc_output trk;
+  catpc_tracks out;
+  int32_t min_hits;
+  int32_t use_graph;
+  bool operator==(const SelKey& o) const { return std::memcmp(this, &o, sizeof(SelKey)) == 0; }
 };
 
 }  // namespace
@@ -100,6 +115,13 @@ struct catpc_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t capture_stream = nullptr;  // the batched chain is captured here, replayed on the caller's stream
+  // last selection call and its graph
+  bool have_sel = false;
+  catpc_tracks sel_out{};
+  bool have_sel_graph = false;
+  SelKey sel_key{};
+  hipGraph_t sel_graph = nullptr;
+  hipGraphExec_t sel_exec = nullptr;
 };
 
 namespace {
@@ -165,6 +187,7 @@ catpc_status check_io(const catpc_ctx* ctx, const catpc_input* in, const catpc_o
 
 Inputs inputs_of(const catpc_input* in) {
   Inputs I;
+  I.x = in->x;
   I.y = in->y;
   I.z = in->z;
   I.row = in->row;
@@ -207,7 +230,7 @@ catpc_status enqueue_span(catpc_ctx* ctx, const catpc_input* in, const catpc_out
   const int nb = ctx->tuning.nf_block;
   auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev[k], st) : hipSuccess; };
   HIP_TRY(mark(0));
-  HIP_TRY(launch_row_index(I, sp, ctx->n_rows, ws, nb, st));
+  HIP_TRY(launch_row_index(I, sp, ctx->n_rows, ctx->row_x, ws, nb, st));
   HIP_TRY(mark(1));
   HIP_TRY(launch_grid(I, sp, ctx->n_rows, ctx->tuning.bin_hits, ws, st));
   HIP_TRY(mark(2));
@@ -224,7 +247,7 @@ catpc_status enqueue_span(catpc_ctx* ctx, const catpc_input* in, const catpc_out
     HIP_TRY(launch_tracklets(I, sp, ctx->n_rows, ctx->row_x, ctx->consts, ws, out->tracklet_offset, 0,
                              out->tracklet_capacity, tracklets_of(out), tc_grid(ctx, (sp.h1 - sp.h0) / 3 + 1),
                              ctx->tuning.tc_block, ctx->tuning.tc_xcd ? kXcds : 1,
-                             ctx->tuning.tc_occupancy, st));
+                             ctx->tuning.tc_occupancy, ctx->tuning.tc_sync, st));
   }
   HIP_TRY(mark(7));
   return CATPC_OK;
@@ -253,6 +276,65 @@ void drop_graph(catpc_ctx* ctx) {
   ctx->exec = nullptr;
   ctx->graph = nullptr;
   ctx->have_graph = false;
+  if (ctx->sel_exec) (void)hipGraphExecDestroy(ctx->sel_exec);
+  if (ctx->sel_graph) (void)hipGraphDestroy(ctx->sel_graph);
+  ctx->sel_exec = nullptr;
+  ctx->sel_graph = nullptr;
+  ctx->have_sel_graph = false;
+}
+
+// Capture `enqueue` on the context's capture stream into (graph, exec) unless
+// the cached graph was made with the same key, then replay it on `st`.
+template <class Key, class F>
+catpc_status replay(catpc_ctx* ctx, bool& have, Key& cached, hipGraph_t& graph, hipGraphExec_t& exec, const Key& k,
+                    F&& enqueue, hipStream_t st) {
+  if (!have || !(k == cached)) {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    have = false;
+    hipStream_t cs = ctx->capture_stream;
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const catpc_status rc = enqueue(cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    const hipError_t e2 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    if (e2 != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return hip_fail(e2, "hipGraphInstantiate");
+    }
+    graph = g;
+    cached = k;
+    have = true;
+  }
+  HIP_TRY(hipGraphLaunch(exec, st));
+  return CATPC_OK;
+}
+
+catpc_status enqueue_select(catpc_ctx* ctx, const catpc_input* in, const catpc_output* trk, const catpc_tracks* out,
+                            hipStream_t st) {
+  TrackletOut T{};
+  T.row_hit = trk->row_hit;
+  T.n_hits = trk->n_hits;
+  T.flags = trk->flags;
+  TracksOut O;
+  O.track_offset = out->track_offset;
+  O.track_tracklet = out->track_tracklet;
+  O.track_n_hits = out->track_n_hits;
+  O.track_hit_offset = out->track_hit_offset;
+  O.track_capacity = out->track_capacity;
+  O.track_hits = out->track_hits;
+  O.hit_capacity = out->hit_capacity;
+  HIP_TRY(launch_select(inputs_of(in), in->n_sectors, trk->tracklet_offset, trk->tracklet_capacity,
+                        ctx->max_hits / 3 + 1, ctx->n_rows, T, ctx->consts, ctx->ws, O, in->n_hits,
+                        ctx->n_cu * 8, st));
+  return CATPC_OK;
 }
 
 }  // namespace
@@ -284,12 +366,13 @@ void catpc_default_tuning(catpc_tuning* t) {
   t->nf_lds_kb = 32;
   t->tc_xcd = 1;
   t->tc_occupancy = 0;
+  t->tc_sync = 0;
 }
 
 int32_t catpc_row_stride(int32_t n_rows) { return n_rows > 0 ? row_stride(n_rows) : 0; }
 
 size_t catpc_workspace_bytes(int32_t n_rows, int64_t max_hits, int32_t max_sectors) {
-  if (n_rows < 3 || max_hits < 0 || max_sectors < 0) return 0;
+  if (n_rows < 3 || n_rows > kMaxRows || max_hits < 0 || max_sectors < 0) return 0;
   return plan(n_rows, max_hits, max_sectors).total + (sizeof(float) + sizeof(float4)) * (size_t)n_rows;
 }
 
@@ -299,7 +382,7 @@ catpc_status catpc_create(int32_t n_rows, const float* row_x, const catpc_params
                           int32_t max_sectors, catpc_ctx** out) {
   if (!out) return fail(CATPC_E_INVALID, "out is NULL");
   *out = nullptr;
-  if (n_rows < 3 || !row_x) return fail(CATPC_E_INVALID, "need n_rows >= 3 and row_x");
+  if (n_rows < 3 || n_rows > kMaxRows || !row_x) return fail(CATPC_E_INVALID, "need 3 <= n_rows <= 4096 and row_x");
   for (int32_t r = 0; r < n_rows; ++r)
     if (!(row_x[r] > 0.0f) || (r > 0 && !(row_x[r] > row_x[r - 1])))
       return fail(CATPC_E_INVALID, "row_x must be positive and strictly ascending");
@@ -360,6 +443,10 @@ catpc_status catpc_create(int32_t n_rows, const float* row_x, const catpc_params
       w.grp_off = (int64_t*)(b + L.grp_off);
       w.start_glob = (int32_t*)(b + L.start_glob);
       w.chain = (ChainHit*)(b + L.chain);
+      w.owner = (unsigned*)(b + L.owner);
+      w.sel_cnt = (int32_t*)(b + L.sel_cnt);
+      w.sel_loc = (int2*)(b + L.sel_loc);
+      w.sel_grp = (longlong2*)(b + L.sel_grp);
       w.counters = (unsigned long long*)(b + L.counters);
       e = hipMemset(w.counters, 0, sizeof(unsigned long long) * kNumCounters);
     }
@@ -407,6 +494,7 @@ catpc_status catpc_set_tuning(catpc_ctx* ctx, const catpc_tuning* t) {
   if (t->tc_xcd < 0 || t->tc_xcd > 1) return fail(CATPC_E_INVALID, "tc_xcd must be 0 or 1");
   if (t->tc_occupancy != 0 && t->tc_occupancy != 5 && t->tc_occupancy != 6 && t->tc_occupancy != 8)
     return fail(CATPC_E_INVALID, "tc_occupancy must be 0, 5, 6 or 8");
+  if (t->tc_sync < 0 || t->tc_sync > 1) return fail(CATPC_E_INVALID, "tc_sync must be 0 or 1");
   ctx->tuning = *t;
   return CATPC_OK;
 }
@@ -423,9 +511,11 @@ catpc_status catpc_track_batch(catpc_ctx* ctx, const catpc_input* in, const catp
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(ctx->device));
   ctx->have_last = false;
+  ctx->have_sel = false;
   if (ctx->tuning.use_graph && in->n_sectors > 0) {
     GraphKey k;
     std::memset(&k, 0, sizeof k);
+    k.in.x = in->x;
     k.in.y = in->y;
     k.in.z = in->z;
     k.in.row = in->row;
@@ -435,28 +525,9 @@ catpc_status catpc_track_batch(catpc_ctx* ctx, const catpc_input* in, const catp
     k.out = *out;
     k.params = ctx->params;
     k.tuning = ctx->tuning;
-    if (!ctx->have_graph || !(k == ctx->key)) {
-      drop_graph(ctx);
-      hipStream_t cs = ctx->capture_stream;
-      HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      rc = enqueue_batch(ctx, in, out, cs);
-      hipGraph_t g = nullptr;
-      hipError_t e = hipStreamEndCapture(cs, &g);
-      if (rc) {
-        if (g) (void)hipGraphDestroy(g);
-        return rc;
-      }
-      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-      e = hipGraphInstantiate(&ctx->exec, g, nullptr, nullptr, 0);
-      if (e != hipSuccess) {
-        (void)hipGraphDestroy(g);
-        return hip_fail(e, "hipGraphInstantiate");
-      }
-      ctx->graph = g;
-      ctx->key = k;
-      ctx->have_graph = true;
-    }
-    HIP_TRY(hipGraphLaunch(ctx->exec, st));
+    rc = replay(ctx, ctx->have_graph, ctx->key, ctx->graph, ctx->exec, k,
+                [&](hipStream_t cs) { return enqueue_batch(ctx, in, out, cs); }, st);
+    if (rc) return rc;
   } else {
     rc = enqueue_batch(ctx, in, out, st);
     if (rc) return rc;
@@ -474,6 +545,7 @@ catpc_status catpc_track_plain(catpc_ctx* ctx, const catpc_input* in, const catp
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(ctx->device));
   ctx->have_last = false;
+  ctx->have_sel = false;
   HIP_TRY(launch_reset(ctx->ws.counters, kNumCounters, st));
   const int64_t* h = in->hit_offset_host;
   for (int32_t s = 0; s < in->n_sectors; ++s) {
@@ -508,6 +580,7 @@ catpc_status catpc_result(catpc_ctx* ctx, void* stream, int64_t* n_tracklets) {
   if (ctx->last_in.n_sectors > 0) total = *ctx->host_total;
   if (n_tracklets) *n_tracklets = total;
   if (ctx->host_counters[kCtrError] & 1ull) return fail(CATPC_E_INVALID, "hits not sorted by row, or a row out of range");
+  if (ctx->host_counters[kCtrError] & 8ull) return fail(CATPC_E_INVALID, "x[i] differs from row_x[row[i]]");
   if (total > ctx->last_out.tracklet_capacity)
     return fail(CATPC_E_CAPACITY, "more tracklets (" + std::to_string(total) + ") than output slots (" +
                                       std::to_string(ctx->last_out.tracklet_capacity) + ")");
@@ -537,7 +610,8 @@ catpc_status catpc_fetch_tracklets(catpc_ctx* ctx, const catpc_input* in, int64_
   HIP_TRY(launch_reset(ctx->ws.counters, kXcds, st));
   HIP_TRY(launch_tracklets(I, sp, ctx->n_rows, ctx->row_x, ctx->consts, ctx->ws, o.tracklet_offset, first,
                            o.tracklet_capacity, tracklets_of(&o), tc_grid(ctx), ctx->tuning.tc_block,
-                           ctx->tuning.tc_xcd ? kXcds : 1, ctx->tuning.tc_occupancy, st));
+                           ctx->tuning.tc_xcd ? kXcds : 1, ctx->tuning.tc_occupancy,
+                           ctx->tuning.tc_sync, st));
   return enqueue_refit(ctx, in, &o, sp, first, st);
 }
 
@@ -549,6 +623,7 @@ catpc_status catpc_stage_times(catpc_ctx* ctx, const catpc_input* in, const catp
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(ctx->device));
   ctx->have_last = false;
+  ctx->have_sel = false;
   hipEvent_t ev[CATPC_N_STAGES + 1] = {};
   for (int k = 0; k <= CATPC_N_STAGES; ++k) HIP_TRY(hipEventCreate(&ev[k]));
   HIP_TRY(launch_reset(ctx->ws.counters, kNumCounters, st));
@@ -586,6 +661,87 @@ catpc_status catpc_work_counts(catpc_ctx* ctx, void* stream, int64_t* counts) {
 catpc_status catpc_fp32_probe(int32_t op, const float* a, const float* b, float* out, int64_t n, void* stream) {
   if (op < 0 || op > 4 || n < 0 || (n > 0 && (!a || !b || !out))) return fail(CATPC_E_INVALID, "bad probe arguments");
   HIP_TRY(launch_fp32_probe(op, a, b, out, n, (hipStream_t)stream));
+  return CATPC_OK;
+}
+
+catpc_status catpc_select_tracklets(catpc_ctx* ctx, const catpc_input* in, const catpc_output* trk,
+                                    const catpc_tracks* out, void* stream) {
+  if (!ctx || !in || !trk || !out) return fail(CATPC_E_INVALID, "NULL argument");
+  if (in->n_sectors < 0 || in->n_sectors > ctx->max_sectors || in->n_hits < 0 || in->n_hits > ctx->max_hits)
+    return fail(CATPC_E_INVALID, "sizes beyond the context's maxima");
+  if (in->n_sectors > 0 && !in->hit_offset) return fail(CATPC_E_INVALID, "hit_offset is NULL");
+  if (!trk->tracklet_offset) return fail(CATPC_E_INVALID, "tracklet_offset is NULL");
+  if (trk->tracklet_capacity < 0) return fail(CATPC_E_INVALID, "tracklet_capacity < 0");
+  if (trk->tracklet_capacity > 0 && (!trk->row_hit || !trk->n_hits || !trk->flags))
+    return fail(CATPC_E_INVALID, "row_hit, n_hits and flags are required");
+  if (trk->tracklet_capacity > 0 && ((uintptr_t)trk->row_hit & 15))
+    return fail(CATPC_E_INVALID, "row_hit is not 16-byte aligned");
+  if (!out->track_offset) return fail(CATPC_E_INVALID, "track_offset is NULL");
+  if (out->track_capacity < 0 || out->hit_capacity < 0) return fail(CATPC_E_INVALID, "negative capacity");
+  if (out->track_capacity > 0 && (!out->track_tracklet || !out->track_n_hits || !out->track_hit_offset))
+    return fail(CATPC_E_INVALID, "track arrays are NULL");
+  if (out->hit_capacity > 0 && !out->track_hits) return fail(CATPC_E_INVALID, "track_hits is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  ctx->have_sel = false;
+  catpc_status rc;
+  if (ctx->tuning.use_graph) {
+    SelKey k;
+    std::memset(&k, 0, sizeof k);
+    k.in.y = in->y;
+    k.in.z = in->z;
+    k.in.row = in->row;
+    k.in.hit_offset = in->hit_offset;
+    k.in.n_sectors = in->n_sectors;
+    k.in.n_hits = in->n_hits;
+    k.trk = *trk;
+    k.out = *out;
+    k.min_hits = ctx->params.min_hits;
+    k.use_graph = 1;
+    rc = replay(ctx, ctx->have_sel_graph, ctx->sel_key, ctx->sel_graph, ctx->sel_exec, k,
+                [&](hipStream_t cs) { return enqueue_select(ctx, in, trk, out, cs); }, st);
+  } else {
+    rc = enqueue_select(ctx, in, trk, out, st);
+  }
+  if (rc) return rc;
+  ctx->sel_out = *out;
+  ctx->have_sel = true;
+  return CATPC_OK;
+}
+
+catpc_status catpc_select_result(catpc_ctx* ctx, void* stream, int64_t* n_tracks, int64_t* n_track_hits) {
+  if (!ctx) return fail(CATPC_E_INVALID, "ctx is NULL");
+  if (!ctx->have_sel) return fail(CATPC_E_STATE, "no selection call since the last track call");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipMemcpyAsync(ctx->host_counters, ctx->ws.counters, sizeof(unsigned long long) * kNumCounters,
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const int64_t nt = (int64_t)ctx->host_counters[kCtrSelTracks], nh = (int64_t)ctx->host_counters[kCtrSelHits];
+  if (n_tracks) *n_tracks = nt;
+  if (n_track_hits) *n_track_hits = nh;
+  const unsigned long long err = ctx->host_counters[kCtrError];
+  if (err & 4ull) return fail(CATPC_E_INVALID, "a tracklet record names a hit outside its sector");
+  if (err & 16ull) return fail(CATPC_E_CAPACITY, "a sector has more tracklets than the selection weights order");
+  if (err & 2ull) return fail(CATPC_E_CAPACITY, "the tracklet output holds only part of the tracklets");
+  if (nt > ctx->sel_out.track_capacity || nh > ctx->sel_out.hit_capacity)
+    return fail(CATPC_E_CAPACITY, "more tracks (" + std::to_string(nt) + ") or track hits (" + std::to_string(nh) +
+                                      ") than the output holds");
+  return CATPC_OK;
+}
+
+catpc_status catpc_probe_copy(const void* src, void* dst, int64_t n_bytes, void* stream) {
+  if (n_bytes < 0 || n_bytes % 16 || (n_bytes > 0 && (!src || !dst)) || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15))
+    return fail(CATPC_E_INVALID, "probe_copy needs 16-byte aligned pointers and a size that is a multiple of 16");
+  if (n_bytes / 16 > (int64_t)UINT32_MAX * 1024) return fail(CATPC_E_INVALID, "probe_copy size too large");
+  HIP_TRY(launch_probe_copy(src, dst, n_bytes / 16, (hipStream_t)stream));
+  return CATPC_OK;
+}
+
+catpc_status catpc_probe_fma(float* out, int64_t n_threads, int32_t n_iter, void* stream) {
+  if (n_threads < 0 || n_iter < 0 || (n_threads > 0 && !out) || n_threads > (int64_t)UINT32_MAX * 256)
+    return fail(CATPC_E_INVALID, "bad probe_fma arguments");
+  HIP_TRY(launch_probe_fma(out, n_threads, n_iter, (hipStream_t)stream));
   return CATPC_OK;
 }
 

@@ -60,13 +60,21 @@ struct Workspace {
   int64_t* grp_off;      // [H/256/1024 + 8] first slot of each group of 1024 blocks
   int32_t* start_glob;   // [H] global hit index of each tracklet slot
   ChainHit* chain;       // [H] coordinates + cleaned up-link per hit (input order)
+  unsigned* owner;               // [H] tracklet selection: weight of the tracklet that keeps each hit
+  int32_t* sel_cnt;              // [H/3 + 2] hits a selected tracklet keeps, or -1
+  int2* sel_loc;                 // [H/3 + 2] track and hit offsets within the slot's group of 1024
+  longlong2* sel_grp;            // [(H/3)/1024 + 8] group offsets
   unsigned long long* counters; // [kNumCounters], see kCtr*
 };
 
 constexpr int kXcds = 8;         // MI355X: 8 accelerator dies, workgroups dispatched round-robin over them
 constexpr int kCtrWork = 0;      // [0, kXcds): work counters of the tracklet kernel, one per slot partition
-constexpr int kCtrError = 8;     // bit 0: invalid rows seen
+constexpr int kCtrError = 8;     // bit 0: invalid rows seen; bit 1: selection saw only part of the tracklets;
+                                 // bit 2: a tracklet record names a hit outside its sector; bit 3: x differs
+                                 // from the row planes; bit 4: too many tracklets in a sector for the selection
 constexpr int kCtrCounts = 9;    // [9, 13): transports, updates, gated candidates, row searches
+constexpr int kCtrSelTracks = 13;  // selected tracks
+constexpr int kCtrSelHits = 14;    // hits they keep
 constexpr int kNumCounters = 16;
 
 // Call geometry: sectors [s0, s1), hits [h0, h1) (global indices).
@@ -76,10 +84,21 @@ struct Span {
 };
 
 struct Inputs {
+  const float* x;  // NULL or checked against the row planes
   const float* y;
   const float* z;
   const int32_t* row;
   const int64_t* hit_offset;
+};
+
+struct TracksOut {
+  int64_t* track_offset;
+  int32_t* track_tracklet;
+  int32_t* track_n_hits;
+  int64_t* track_hit_offset;
+  int64_t track_capacity;
+  int32_t* track_hits;
+  int64_t hit_capacity;
 };
 
 struct TrackletOut {
@@ -97,13 +116,15 @@ struct TrackletOut {
 // Row stride of the hit-per-row output (whole chunks of 8 rows).
 __host__ __device__ inline int row_stride(int R) { return (R + 7) & ~7; }
 
+constexpr int kMaxRows = 4096;       // pad rows per sector (row indices are wave-reduced as 16-bit values)
 constexpr int kHitsPerBlock = 256;  // per-hit kernels: block size of clean/start/compaction
 constexpr int kMaxBinsPerRow = 1024;
 constexpr float kBinMargin = 1.0e-2f;  // cm, widens bin ranges beyond rounding of window edges
 
 // Launchers (kernels.hip).  All asynchronous on `st`.
 hipError_t launch_reset(unsigned long long* counters, int n, hipStream_t st);
-hipError_t launch_row_index(const Inputs& in, Span sp, int n_rows, const Workspace& ws, int block, hipStream_t st);
+hipError_t launch_row_index(const Inputs& in, Span sp, int n_rows, const float* row_x, const Workspace& ws,
+                            int block, hipStream_t st);
 hipError_t launch_grid(const Inputs& in, Span sp, int n_rows, float bin_hits, const Workspace& ws, hipStream_t st);
 hipError_t launch_neighbours(const Inputs& in, Span sp, int n_rows, const float4* rowk, const Consts& c,
                              const Workspace& ws, int32_t* up, int32_t* dn, int block, int rows, int lds_bytes,
@@ -115,10 +136,16 @@ hipError_t launch_compact(const Inputs& in, Span sp, int64_t* toff, int32_t* sta
                           hipStream_t st);
 hipError_t launch_tracklets(const Inputs& in, Span sp, int n_rows, const float* row_x, const Consts& c,
                             const Workspace& ws, const int64_t* toff, int64_t first, int64_t cap,
-                            const TrackletOut& out, int grid, int block, int nparts, int waves, hipStream_t st);
+                            const TrackletOut& out, int grid, int block, int nparts, int waves, int sync,
+                            hipStream_t st);
+hipError_t launch_select(const Inputs& in, int S, const int64_t* toff, int64_t cap, int64_t max_slots, int n_rows,
+                         const TrackletOut& trk, const Consts& c, const Workspace& ws, const TracksOut& out,
+                         int64_t n_hits, int grid, hipStream_t st);
 hipError_t launch_refit64(const Inputs& in, Span sp, int n_rows, const float* row_x, const Consts& c,
                           const Workspace& ws, const int64_t* toff, int64_t first, int64_t cap,
                           const TrackletOut& out, int grid, hipStream_t st);
+hipError_t launch_probe_copy(const void* src, void* dst, int64_t n16, hipStream_t st);
+hipError_t launch_probe_fma(float* out, int64_t n, int iters, hipStream_t st);
 hipError_t launch_fp32_probe(int op, const float* a, const float* b, float* out, int64_t n, hipStream_t st);
 
 }  // namespace catpc

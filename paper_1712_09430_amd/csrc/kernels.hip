@@ -26,6 +26,8 @@
 //               following, back-transport, inward following
 //   refit64     one lane per tracklet needing it: binary64-covariance refit
 #include <float.h>
+
+#include <algorithm>
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -90,9 +92,9 @@ __global__ void k_reset(unsigned long long* c, int n) {
 // of the row by binary search (monotone in r for any input; row 0 starts at
 // the sector's first hit and row R at its end, so the rows always partition
 // the sector).  Remaining blocks: one thread per hit, order and range check.
-__global__ __launch_bounds__(256) void k_row_index(Inputs in, Span sp, int R, int32_t* row_first,
-                                                   unsigned long long* counters, int64_t n_items,
-                                                   int64_t item_blocks) {
+__global__ __launch_bounds__(256) void k_row_index(Inputs in, Span sp, int R, const float* __restrict__ row_x,
+                                                   int32_t* row_first, unsigned long long* counters,
+                                                   int64_t n_items, int64_t item_blocks) {
   if ((int64_t)blockIdx.x < item_blocks) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_items) return;
@@ -114,6 +116,7 @@ __global__ __launch_bounds__(256) void k_row_index(Inputs in, Span sp, int R, in
       bool ok = r >= 0 && r < R;
       if (i > in.hit_offset[s]) ok = ok && in.row[i - 1] <= r;
       if (!ok) atomicOr(&counters[kCtrError], 1ull);
+      if (ok && in.x && !(in.x[i] == row_x[r])) atomicOr(&counters[kCtrError], 8ull);
     }
   }
 }
@@ -799,7 +802,29 @@ struct Seed {
 
 constexpr int kTcMaxBlock = 256;
 
+// Smallest / largest v over the wave's active lanes, 0 <= v < 2^16, from
+// ballots (the result is wave-uniform).
+__device__ __forceinline__ int wave_min16(int v) {
+  int m = 0;
+#pragma unroll
+  for (int b = 15; b >= 0; --b)
+    if (!__ballot(v < m + (1 << b))) m += 1 << b;
+  return m;
+}
+
+__device__ __forceinline__ int wave_max16(int v) {
+  int m = 0;
+#pragma unroll
+  for (int b = 15; b >= 0; --b)
+    if (__ballot(v >= m + (1 << b))) m += 1 << b;
+  return m;
+}
+
 // One tracklet: slot -> start hit -> seed chain -> following -> output.
+// kSync: the lanes of a wave walk the pad rows together (a lane whose pass
+// starts later waits), so that they read the same row grids at the same time;
+// each lane's own sequence of filter steps is the same either way.
+template <bool kSync>
 __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __restrict__ row_x, const Consts& c,
                                const Workspace& ws, const int64_t* toff, int64_t slot, int64_t o,
                                const TrackletOut& out, int RS, int32_t* chunk_lds, Work& w) {
@@ -830,7 +855,9 @@ __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __
     // seed chain (no gate), then outward following
     int32_t h = h1;
     int miss = 0;
-    for (int r = r0 + 1; r < R; ++r) {
+    const int r_first = kSync ? wave_min16(r0 + 1) : r0 + 1;
+    for (int r = r_first; r < R; ++r) {
+      if (kSync && r <= r0) continue;  // waits for the wave's row
       RowHdr hd;
       if (h < 0) hd = ws.hdr[(int64_t)s * R + r];  // issued before the transport arithmetic
       ++w.n_prop;
@@ -870,33 +897,41 @@ __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __
     st = snap;  // inward: snap becomes the state at the innermost update
     miss = 0;
     k.c = k0;
-    for (int r = lastr - 1; r >= 0; --r) {
-      RowHdr hd;
-      if (r < r0) hd = ws.hdr[(int64_t)s * R + r];
+    bool back_ok = true;
+    for (int r = lastr - 1; r >= r0; --r) {  // back to the start row, no updates
       ++w.n_prop;
       const int e = propagate(st, row_x[r], c);
-      if (e) { fl |= stop_flag(e); break; }
-      if (r > r0) continue;
-      if (r == r0) { snap = st; continue; }
-      if ((r >> 3) != k.c) {
-        if (k.c < k0) chunk_store(k, rec);
-        chunk_clear(k, r >> 3);
-        k_lo = r >> 3;
-      }
-      const Pick j = closest(st, grid_of(hd, ws), c, w);
-      if (j.idx >= 0) {
-        ++w.n_upd;
-        if (update(st, j.y, j.z, c)) { fl |= 2; break; }
-        snap = st;
-        if (k.c == k0)
-          rec[r] = j.idx;
-        else
-          chunk_set(k, r, j.idx);
-        ++nh;
-        first_row = r;
-        miss = 0;
-      } else if (++miss > c.max_miss) {
-        break;
+      if (e) { fl |= stop_flag(e); back_ok = false; break; }
+    }
+    if (back_ok) {
+      snap = st;
+      const int r_top = (kSync ? wave_max16(r0) : r0) - 1;
+      for (int r = r_top; r >= 0; --r) {
+        if (kSync && r >= r0) continue;  // waits for the wave's row
+        const RowHdr hd = ws.hdr[(int64_t)s * R + r];  // issued before the transport arithmetic
+        ++w.n_prop;
+        const int e = propagate(st, row_x[r], c);
+        if (e) { fl |= stop_flag(e); break; }
+        if ((r >> 3) != k.c) {
+          if (k.c < k0) chunk_store(k, rec);
+          chunk_clear(k, r >> 3);
+          k_lo = r >> 3;
+        }
+        const Pick j = closest(st, grid_of(hd, ws), c, w);
+        if (j.idx >= 0) {
+          ++w.n_upd;
+          if (update(st, j.y, j.z, c)) { fl |= 2; break; }
+          snap = st;
+          if (k.c == k0)
+            rec[r] = j.idx;
+          else
+            chunk_set(k, r, j.idx);
+          ++nh;
+          first_row = r;
+          miss = 0;
+        } else if (++miss > c.max_miss) {
+          break;
+        }
       }
     }
     if (k.c < k0) chunk_store(k, rec);
@@ -916,7 +951,7 @@ __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __
 
 // kWaves > 0 asks the compiler to fit the kernel's registers for at least
 // kWaves resident waves per SIMD (spilling to scratch where needed).
-template <int kWaves>
+template <int kWaves, bool kSync>
 __global__ __launch_bounds__(kTcMaxBlock) __attribute__((amdgpu_waves_per_eu(kWaves > 0 ? kWaves : 1))) void
 k_tracklets(Inputs in, Span sp, int R, const float* __restrict__ row_x, Consts c, Workspace ws, const int64_t* toff,
             int64_t first, int64_t cap, TrackletOut out, int nparts) {
@@ -932,9 +967,295 @@ k_tracklets(Inputs in, Span sp, int R, const float* __restrict__ row_x, Consts c
     const int64_t slot0 = take_slots(P, k, ws.counters + kCtrWork, 64, lane, pend);
     if (slot0 < 0) break;
     const int64_t slot = slot0 + lane;
-    if (slot < pend) build_tracklet(in, sp, R, row_x, c, ws, toff, slot, slot - first, out, row_stride(R), chunk_lds, w);
+    if (slot < pend) build_tracklet<kSync>(in, sp, R, row_x, c, ws, toff, slot, slot - first, out, row_stride(R), chunk_lds,
+                                             w);
   }
   flush_work(w, ws, lane);
+}
+
+// ------------------------------------------------------- tracklet selection
+// Of several tracklets that share hits the best keeps them (Sec. 2 item 2):
+// the weight of a tracklet is its hit count, then the smaller sector-local
+// tracklet index; every hit goes to the heaviest valid tracklet listing it
+// (one 64-bit atomic maximum per hit, so the result does not depend on the
+// order of the atomics); a tracklet is selected when it keeps at least
+// min_hits hits, and its track is the list of hits it keeps, rows ascending.
+// 32-bit weight: the hit count (at most R, in hbits = bits of R) above the
+// complement of the tracklet index (the remaining bits; a sector with more
+// tracklets than they hold is reported, not selected).
+__device__ __forceinline__ unsigned sel_weight(int32_t n, int32_t t, int lbits) {
+  const unsigned lmask = (1u << lbits) - 1u;
+  return ((unsigned)n << lbits) | (lmask - ((unsigned)t & lmask));
+}
+
+__host__ __device__ inline int sel_index_bits(int R) {
+  int hb = 0;
+  while ((1 << hb) <= R) ++hb;
+  return 32 - hb;
+}
+
+// Slots of the selection: the tracklets present in the output buffer
+// (`slots` = its capacity, clamped to the workspace's slot count).
+__device__ __forceinline__ int64_t sel_slots(const int64_t* toff, int S, int64_t slots) {
+  return max((int64_t)0, min(toff[S], slots));
+}
+
+
+// The selection kernels give each tracklet 16 lanes (4 tracklets per wave):
+// lane l of a group reads the 16-byte pieces l, l+16, l+32 of the record, so
+// the record is read with coalesced loads and the per-hit work of a tracklet
+// is spread over its lanes.  Persistent grid-stride loop over the slots.
+constexpr int kSelLanes = 16;
+
+struct SelTrk {
+  int64_t slot, a;
+  int32_t ns, local;
+  unsigned key;
+  bool on;  // a valid tracklet of this group
+};
+
+__device__ __forceinline__ SelTrk sel_trk(const Inputs& in, int S, const int64_t* toff, const TrackletOut& trk,
+                                          int64_t slot, int64_t n, int lbits) {
+  SelTrk t;
+  t.slot = slot;
+  t.on = slot < n && (trk.flags[slot] & 1) != 0;
+  t.a = 0;
+  t.ns = 0;
+  t.local = 0;
+  t.key = 0;
+  if (t.on) {
+    const int s = sector_of(toff, 0, S, slot);
+    t.a = in.hit_offset[s];
+    t.ns = (int32_t)(in.hit_offset[s + 1] - t.a);
+    t.local = (int32_t)(slot - toff[s]);
+    t.key = sel_weight(trk.n_hits[slot], t.local, lbits);
+  }
+  return t;
+}
+
+// Claim: one workgroup per (sector, chunk of kSelRows rows).  The owner
+// words of the chunk's hits (contiguous, the hits being sorted by row) are
+// kept in LDS while every valid tracklet of the sector takes the atomic
+// maximum of its weight on its hits in these rows, then written out whole
+// (which also clears the words of hits nobody lists).  A chunk with more hits
+// than the LDS holds works on the owner words in memory instead.
+constexpr int kSelRows = 16;
+
+// Clears the selection's error bits before a selection.
+__global__ void k_sel_flags(Workspace ws) {
+  if (threadIdx.x == 0) atomicAnd(&ws.counters[kCtrError], ~(2ull | 4ull | 16ull));
+}
+
+constexpr int kSelLdsWords = 8192;
+
+__global__ __launch_bounds__(256) void k_sel_claim(Inputs in, int S, const int64_t* toff, int64_t slots, int R,
+                                                   TrackletOut trk, Workspace ws) {
+  __shared__ unsigned own[kSelLdsWords];
+  const int nch = (R + kSelRows - 1) / kSelRows;
+  const int s = (int)(blockIdx.x / nch);
+  const int r0 = (int)(blockIdx.x % nch) * kSelRows;
+  const int r1 = min(R, r0 + kSelRows);
+  const int64_t n = sel_slots(toff, S, slots);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && toff[S] > slots) atomicOr(&ws.counters[kCtrError], 2ull);
+  const int32_t* rf = ws.row_first + (int64_t)s * (R + 1);
+  const int32_t h_lo = rf[r0], h_hi = rf[r1];
+  const int nh = h_hi - h_lo;
+  const int64_t a = in.hit_offset[s];
+  unsigned* gown = ws.owner + a + h_lo;
+  const bool lds = nh <= kSelLdsWords;
+  for (int k = threadIdx.x; k < nh; k += blockDim.x) {
+    if (lds) own[k] = 0u; else gown[k] = 0u;
+  }
+  if (!lds) __threadfence();
+  __syncthreads();
+  const int lbits = sel_index_bits(R);
+  const int64_t t0 = min(toff[s], n), t1 = min(toff[s + 1], n);
+  const int RS = row_stride(R);
+  bool bad = false, many = false;
+  for (int64_t slot = t0 + threadIdx.x; slot < t1; slot += blockDim.x) {
+    if (!(trk.flags[slot] & 1)) continue;
+    const int32_t local = (int32_t)(slot - toff[s]);
+    if (local >= (1 << lbits)) { many = true; continue; }
+    const unsigned key = sel_weight(trk.n_hits[slot], local, lbits);
+    const int4* rec = reinterpret_cast<const int4*>(trk.row_hit + slot * RS + r0);
+    for (int q = 0; q < (r1 - r0 + 3) / 4; ++q) {
+      const int4 v = rec[q];
+      const int32_t hv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int32_t h = hv[m];
+        if (h < 0 || 4 * q + m >= r1 - r0) continue;
+        const int32_t hl = h - h_lo;
+        if (hl < 0 || hl >= nh) { bad = true; continue; }  // not a hit of these rows
+        if (lds) atomicMax(&own[hl], key); else atomicMax(&gown[hl], key);
+      }
+    }
+  }
+  if (bad) atomicOr(&ws.counters[kCtrError], 4ull);
+  if (many) atomicOr(&ws.counters[kCtrError], 16ull);
+  if (lds) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < nh; k += blockDim.x) gown[k] = own[k];
+  }
+}
+
+// Count: 16 lanes per tracklet, the hits whose owner is this tracklet.
+__global__ __launch_bounds__(256) void k_sel_count(Inputs in, int S, const int64_t* toff, int64_t slots, int R,
+                                                   TrackletOut trk, Consts c, Workspace ws) {
+  const int64_t n = sel_slots(toff, S, slots);
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lbits = sel_index_bits(R);
+  const int sub = threadIdx.x & (kSelLanes - 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x / kSelLanes;
+  const int RS4 = row_stride(R) / 4;
+  for (int64_t slot = gtid / kSelLanes; slot < n; slot += stride) {
+    const SelTrk t = sel_trk(in, S, toff, trk, slot, n, lbits);
+    int cnt = 0;
+    if (t.on && t.local < (1 << lbits)) {
+      const int4* rec = reinterpret_cast<const int4*>(trk.row_hit + slot * row_stride(R));
+      for (int q = sub; q < RS4; q += kSelLanes) {
+        const int4 v = rec[q];
+        const int32_t hv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int32_t h = hv[m];
+          if (h >= 0 && h < t.ns) cnt += ws.owner[t.a + h] == t.key;
+        }
+      }
+    }
+    for (int o = kSelLanes / 2; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, kSelLanes);
+    if (sub == 0) ws.sel_cnt[slot] = (t.on && cnt >= c.min_hits) ? cnt : -1;
+  }
+}
+
+// Exclusive scans over the slots: selected tracks and their kept hits, 1024
+// slots per workgroup (offsets relative to the group), then the group totals.
+__global__ __launch_bounds__(kScanGroup) void k_sel_scan_local(const int64_t* toff, int S, int64_t slots,
+                                                                 Workspace ws) {
+  __shared__ int wsum[2][kScanGroup / 64];
+  const int64_t n = sel_slots(toff, S, slots);
+  const int64_t b = (int64_t)blockIdx.x * kScanGroup + threadIdx.x;
+  const int cv = b < n ? ws.sel_cnt[b] : -1;
+  const int vt = cv >= 0 ? 1 : 0, vh = cv >= 0 ? cv : 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int it = vt, ih = vh;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int ut = __shfl_up(it, o), uh = __shfl_up(ih, o);
+    if (lane >= o) { it += ut; ih += uh; }
+  }
+  if (lane == 63) { wsum[0][wave] = it; wsum[1][wave] = ih; }
+  __syncthreads();
+  if (wave == 0) {
+    int xt = lane < kScanGroup / 64 ? wsum[0][lane] : 0, xh = lane < kScanGroup / 64 ? wsum[1][lane] : 0;
+    for (int o = 1; o < kScanGroup / 64; o <<= 1) {
+      const int ut = __shfl_up(xt, o), uh = __shfl_up(xh, o);
+      if (lane >= o) { xt += ut; xh += uh; }
+    }
+    if (lane < kScanGroup / 64) { wsum[0][lane] = xt; wsum[1][lane] = xh; }
+  }
+  __syncthreads();
+  if (b <= n) {
+    const int bt = wave ? wsum[0][wave - 1] : 0, bh = wave ? wsum[1][wave - 1] : 0;
+    ws.sel_loc[b] = make_int2(bt + it - vt, bh + ih - vh);
+  }
+  if (threadIdx.x == kScanGroup - 1)
+    ws.sel_grp[blockIdx.x] = make_longlong2(wsum[0][kScanGroup / 64 - 1], wsum[1][kScanGroup / 64 - 1]);
+}
+
+__global__ __launch_bounds__(1024) void k_sel_scan_top(int64_t ng, Workspace ws) {
+  __shared__ int64_t pt[1024], ph[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (ng + 1023) / 1024;
+  const int64_t g0 = min(ng, (int64_t)t * per), g1 = min(ng, g0 + per);
+  int64_t st = 0, sh = 0;
+  for (int64_t g = g0; g < g1; ++g) { st += ws.sel_grp[g].x; sh += ws.sel_grp[g].y; }
+  pt[t] = st;
+  ph[t] = sh;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int64_t vt = t >= o ? pt[t - o] : 0, vh = t >= o ? ph[t - o] : 0;
+    __syncthreads();
+    pt[t] += vt;
+    ph[t] += vh;
+    __syncthreads();
+  }
+  int64_t rt = pt[t] - st, rh = ph[t] - sh;
+  for (int64_t g = g0; g < g1; ++g) {
+    const longlong2 v = ws.sel_grp[g];
+    ws.sel_grp[g] = make_longlong2(rt, rh);
+    rt += v.x;
+    rh += v.y;
+  }
+  if (t == 1023) {
+    ws.sel_grp[ng] = make_longlong2(pt[1023], ph[1023]);
+    ws.counters[kCtrSelTracks] = (unsigned long long)pt[1023];
+    ws.counters[kCtrSelHits] = (unsigned long long)ph[1023];
+  }
+}
+
+__device__ __forceinline__ longlong2 sel_offset(const Workspace& ws, int64_t b) {
+  const longlong2 g = ws.sel_grp[b / kScanGroup];
+  const int2 l = ws.sel_loc[b];
+  return make_longlong2(g.x + l.x, g.y + l.y);
+}
+
+// Each selected tracklet writes its track (16 lanes, the kept hits in row
+// order through a prefix count over the lanes); the grid's first S+1 threads
+// also write the first track of each sector.
+__global__ __launch_bounds__(256) void k_sel_emit(Inputs in, int S, const int64_t* toff, int64_t slots, int R,
+                                                  TrackletOut trk, Workspace ws, TracksOut out) {
+  const int64_t n = sel_slots(toff, S, slots);
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t s = gtid; s <= S; s += nthreads) {
+    const int64_t q = max((int64_t)0, min(toff[s], n));
+    out.track_offset[s] = sel_offset(ws, q).x;
+  }
+  const int sub = threadIdx.x & (kSelLanes - 1);
+  const int64_t stride = nthreads / kSelLanes;
+  const int RS4 = row_stride(R) / 4;
+  for (int64_t slot = gtid / kSelLanes; slot < n; slot += stride) {
+    const int cnt = ws.sel_cnt[slot];
+    if (cnt < 0) continue;  // the 16 lanes of a slot take this branch together
+    const SelTrk t = sel_trk(in, S, toff, trk, slot, n, sel_index_bits(R));
+    const longlong2 off = sel_offset(ws, slot);
+    if (sub == 0 && off.x < out.track_capacity) {
+      out.track_tracklet[off.x] = t.local;
+      out.track_n_hits[off.x] = cnt;
+      out.track_hit_offset[off.x] = off.y;
+    }
+    const int4* rec = reinterpret_cast<const int4*>(trk.row_hit + slot * row_stride(R));
+    int64_t base = off.y;
+    for (int q0 = 0; q0 < RS4; q0 += kSelLanes) {
+      const int q = q0 + sub;
+      int32_t w[4] = {-1, -1, -1, -1};
+      bool own[4] = {false, false, false, false};
+      int mine = 0;
+      if (q < RS4) {
+        const int4 v = rec[q];
+        w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          own[m] = w[m] >= 0 && w[m] < t.ns && ws.owner[t.a + w[m]] == t.key;
+          mine += own[m];
+        }
+      }
+      // kept hits of the lanes before this one in this round (rows ascend with q)
+      int incl = mine;
+      for (int o = 1; o < kSelLanes; o <<= 1) {
+        const int u = __shfl_up(incl, o, kSelLanes);
+        if (sub >= o) incl += u;
+      }
+      int64_t k = base + incl - mine;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        if (!own[m]) continue;
+        if (k < out.hit_capacity) out.track_hits[k] = w[m];
+        ++k;
+      }
+      base += __shfl(incl, kSelLanes - 1, kSelLanes);
+    }
+  }
 }
 
 // ------------------------------------------------- binary64-covariance refit
@@ -1100,6 +1421,34 @@ __global__ void k_fp32_probe(int op, const float* a, const float* b, float* o, i
   o[i] = r;
 }
 
+// Achievable-peak probes: a 16-byte-per-lane copy, and 8 independent chains
+// of binary32 fused multiply-adds per thread.
+__global__ __launch_bounds__(256) void k_probe_copy(const int4* __restrict__ src, int4* __restrict__ dst, int64_t n) {
+  const int64_t i0 = ((int64_t)blockIdx.x * 256 * 4) + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t i = i0 + (int64_t)u * 256;
+    if (i < n) dst[i] = src[i];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_probe_fma(float* out, int64_t n, int iters) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float m = 0.9999999f, c = 1.0e-7f;
+  float a[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a[k] = (float)((i + k) & 1023) * 1.0e-3f;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = fmaf(a[k], m, c);
+  }
+  float s = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s += a[k];
+  out[i] = s;
+}
+
 inline unsigned blocks_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 }  // namespace
@@ -1110,12 +1459,13 @@ hipError_t launch_reset(unsigned long long* counters, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_row_index(const Inputs& in, Span sp, int n_rows, const Workspace& ws, int block, hipStream_t st) {
+hipError_t launch_row_index(const Inputs& in, Span sp, int n_rows, const float* row_x, const Workspace& ws,
+                            int block, hipStream_t st) {
   const int64_t n_items = (int64_t)(sp.s1 - sp.s0) * (n_rows + 1);
   const int64_t item_blocks = blocks_for(n_items, block);
   const int64_t total = item_blocks + blocks_for(sp.h1 - sp.h0, block);
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_row_index, dim3((unsigned)total), dim3(block), 0, st, in, sp, n_rows, ws.row_first,
+  hipLaunchKernelGGL(k_row_index, dim3((unsigned)total), dim3(block), 0, st, in, sp, n_rows, row_x, ws.row_first,
                      ws.counters, n_items, item_blocks);
   return hipGetLastError();
 }
@@ -1167,10 +1517,17 @@ hipError_t launch_compact(const Inputs& in, Span sp, int64_t* toff, int32_t* sta
 
 hipError_t launch_tracklets(const Inputs& in, Span sp, int n_rows, const float* row_x, const Consts& c,
                             const Workspace& ws, const int64_t* toff, int64_t first, int64_t cap,
-                            const TrackletOut& out, int grid, int block, int nparts, int waves, hipStream_t st) {
-#define CATPC_TC(K)                                                                                          \
-  hipLaunchKernelGGL(k_tracklets<K>, dim3(grid), dim3(block), 0, st, in, sp, n_rows, row_x, c, ws, toff, first, cap, \
-                     out, nparts)
+                            const TrackletOut& out, int grid, int block, int nparts, int waves, int sync,
+                            hipStream_t st) {
+#define CATPC_TC(K)                                                                                           \
+  do {                                                                                                        \
+    if (sync)                                                                                                 \
+      hipLaunchKernelGGL((k_tracklets<K, true>), dim3(grid), dim3(block), 0, st, in, sp, n_rows, row_x, c, ws,   \
+                         toff, first, cap, out, nparts);                                                      \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_tracklets<K, false>), dim3(grid), dim3(block), 0, st, in, sp, n_rows, row_x, c, ws,  \
+                         toff, first, cap, out, nparts);                                                      \
+  } while (0)
   switch (waves) {
     case 5: CATPC_TC(5); break;
     case 6: CATPC_TC(6); break;
@@ -1181,11 +1538,41 @@ hipError_t launch_tracklets(const Inputs& in, Span sp, int n_rows, const float* 
   return hipGetLastError();
 }
 
+hipError_t launch_select(const Inputs& in, int S, const int64_t* toff, int64_t cap, int64_t max_slots, int n_rows,
+                         const TrackletOut& trk, const Consts& c, const Workspace& ws, const TracksOut& out,
+                         int64_t n_hits, int grid, hipStream_t st) {
+  const int64_t slots = std::min(cap, max_slots);
+  const int64_t ng = slots / kScanGroup + 1;  // covers entries [0, slots]
+  (void)n_hits;
+  hipLaunchKernelGGL(k_sel_flags, dim3(1), dim3(64), 0, st, ws);
+  const int64_t claim_blocks = (int64_t)S * ((n_rows + kSelRows - 1) / kSelRows);
+  if (claim_blocks > 0)
+    hipLaunchKernelGGL(k_sel_claim, dim3((unsigned)claim_blocks), dim3(256), 0, st, in, S, toff, slots, n_rows, trk,
+                       ws);
+  hipLaunchKernelGGL(k_sel_count, dim3(grid), dim3(256), 0, st, in, S, toff, slots, n_rows, trk, c, ws);
+  hipLaunchKernelGGL(k_sel_scan_local, dim3((unsigned)ng), dim3(kScanGroup), 0, st, toff, S, slots, ws);
+  hipLaunchKernelGGL(k_sel_scan_top, dim3(1), dim3(1024), 0, st, ng, ws);
+  hipLaunchKernelGGL(k_sel_emit, dim3(grid), dim3(256), 0, st, in, S, toff, slots, n_rows, trk, ws, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_refit64(const Inputs& in, Span sp, int n_rows, const float* row_x, const Consts& c,
                           const Workspace& ws, const int64_t* toff, int64_t first, int64_t cap,
                           const TrackletOut& out, int grid, hipStream_t st) {
   (void)ws;
   hipLaunchKernelGGL(k_refit64, dim3(grid), dim3(256), 0, st, in, sp, n_rows, row_x, c, toff, first, cap, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_copy(const void* src, void* dst, int64_t n16, hipStream_t st) {
+  if (n16 == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_probe_copy, dim3(blocks_for(n16, 256 * 4)), dim3(256), 0, st, (const int4*)src, (int4*)dst, n16);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_fma(float* out, int64_t n, int iters, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_probe_fma, dim3(blocks_for(n, 256)), dim3(256), 0, st, out, n, iters);
   return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ def _stream(device):
 class DeviceHits:
     """Row-sorted hits of one or more sectors, resident on the device."""
 
-    def __init__(self, y, z, row, hit_offset, device="cuda:0"):
+    def __init__(self, y, z, row, hit_offset, device="cuda:0", x=None):
         dev = _need_gpu(device)
         self.device = dev
         self.hit_offset_host = np.ascontiguousarray(hit_offset, np.int64)
@@ -43,6 +43,8 @@ class DeviceHits:
         s.hit_offset = _ptr(self.hit_offset)
         s.hit_offset_host = ctypes.c_void_p(self.hit_offset_host.ctypes.data)
         s.n_sectors, s.n_hits = self.n_sectors, self.n_hits
+        self.x = None if x is None else torch.as_tensor(np.ascontiguousarray(x, np.float32)).to(dev)
+        s.x = _ptr(self.x)
         self.struct = s
 
 
@@ -92,6 +94,32 @@ class DeviceOutput:
         off = d["tracklet_offset"]
         d["start_hit"] = self.start_hit[:int(off[-1])].cpu().numpy()
         return d
+
+
+class DeviceTracks:
+    """Output buffers of the tracklet selection: at most `track_capacity`
+    tracks and `hit_capacity` track hits (n_hits always suffices)."""
+
+    def __init__(self, n_sectors, track_capacity, hit_capacity, device="cuda:0"):
+        dev = _need_gpu(device)
+        e = lambda n, dt: torch.empty(n, dtype=dt, device=dev)
+        self.track_offset = e(n_sectors + 1, torch.int64)
+        self.track_tracklet = e(track_capacity, torch.int32)
+        self.track_n_hits = e(track_capacity, torch.int32)
+        self.track_hit_offset = e(track_capacity, torch.int64)
+        self.track_hits = e(hit_capacity, torch.int32)
+        s = C.catpc_tracks()
+        for f in ("track_offset", "track_tracklet", "track_n_hits", "track_hit_offset", "track_hits"):
+            setattr(s, f, _ptr(getattr(self, f)))
+        s.track_capacity, s.hit_capacity = int(track_capacity), int(hit_capacity)
+        self.struct = s
+
+    def numpy(self, n_tracks, n_track_hits):
+        return {"track_offset": self.track_offset.cpu().numpy(),
+                "track_tracklet": self.track_tracklet[:n_tracks].cpu().numpy(),
+                "track_n_hits": self.track_n_hits[:n_tracks].cpu().numpy(),
+                "track_hit_offset": self.track_hit_offset[:n_tracks].cpu().numpy(),
+                "track_hits": self.track_hits[:n_track_hits].cpu().numpy()}
 
 
 class Tracker:
@@ -156,6 +184,20 @@ class Tracker:
     def work_counts(self):
         with torch.cuda.device(self.device):
             return C.catpc_work_counts(self.ctx, _stream(self.device))
+
+    def tracks_output(self, hits, out):
+        """Selection buffers that always suffice for this output."""
+        return DeviceTracks(hits.n_sectors, out.capacity, max(hits.n_hits, 1), self.device)
+
+    def select(self, hits, out, tracks):
+        """Enqueue the tracklet selection of the last track call's output."""
+        with torch.cuda.device(self.device):
+            C.catpc_select_tracklets(self.ctx, hits.struct, out.struct, tracks.struct, _stream(self.device))
+
+    def select_result(self):
+        """Synchronise; (n_tracks, n_track_hits)."""
+        with torch.cuda.device(self.device):
+            return C.catpc_select_result(self.ctx, _stream(self.device))
 
     def fetch(self, hits, first, out):
         with torch.cuda.device(self.device):

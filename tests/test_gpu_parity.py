@@ -129,11 +129,11 @@ def test_tuning_does_not_change_results():
     b = synth.batch_workload(seed=5, n_events=2, lo=200, hi=3000)
     _, _, _, n0, l0, t0 = check_batch(b, sectors=[0, 17, 40])
     for tun in ({"bin_hits": 0.5, "nf_block": 64, "tc_block": 64, "tc_waves_per_cu": 1, "use_graph": 0,
-                 "nf_rows": 1, "nf_lds_kb": 0, "tc_xcd": 0, "tc_occupancy": 8},
+                 "nf_rows": 1, "nf_lds_kb": 0, "tc_xcd": 0, "tc_occupancy": 8, "tc_sync": 1},
                 {"bin_hits": 16.0, "nf_block": 128, "tc_block": 128, "tc_waves_per_cu": 32, "use_graph": 1,
                  "nf_rows": 16, "nf_lds_kb": 64, "tc_xcd": 1, "tc_occupancy": 8},
                 {"bin_hits": 1.0, "nf_block": 256, "tc_block": 256, "tc_waves_per_cu": 3, "use_graph": 1,
-                 "nf_rows": 3, "nf_lds_kb": 8, "tc_xcd": 1, "tc_occupancy": 6},
+                 "nf_rows": 3, "nf_lds_kb": 8, "tc_xcd": 1, "tc_occupancy": 6, "tc_sync": 1},
                 {"bin_hits": 0.5, "nf_block": 64, "tc_block": 64, "tc_waves_per_cu": 2, "use_graph": 0,
                  "nf_rows": 2, "nf_lds_kb": 32, "tc_xcd": 0, "tc_occupancy": 6}):
         _, _, out, st, n = run_gpu(b, tuning=tun)
@@ -264,3 +264,29 @@ def test_invariants_and_one_hypothesis_per_seed():
     assert rs % 8 == 0 and rs >= len(b.row_x) and out.row_hit.shape[1] == rs
     pad = out.row_hit[:n, len(b.row_x):].cpu().numpy()
     assert pad.size == 0 or np.all(pad == -1)
+
+
+def test_x_input_is_checked_against_the_row_planes():
+    _torch()
+    from paper_1712_09430_amd import catpc as C
+    from paper_1712_09430_amd.tracker import DeviceHits, Tracker
+    b = synth.batch_workload(seed=8, n_events=2, lo=100, hi=800)
+    assert np.array_equal(b.x, b.row_x[b.row])  # the generator puts hits on the row planes
+    tr = Tracker(b.row_x, b.n_hits, b.n_sectors)
+    ref = DeviceHits(b.y, b.z, b.row, b.hit_offset)
+    out0 = tr.output(ref)
+    tr.track(ref, out0)
+    st, n = tr.result()
+    with_x = DeviceHits(b.y, b.z, b.row, b.hit_offset, x=b.x)
+    out1 = tr.output(with_x)
+    tr.track(with_x, out1)
+    st1, n1 = tr.result()
+    assert st == st1 == C.CATPC_OK and n == n1
+    assert np.array_equal(out0.tracklets_numpy(n)["param"].view(np.uint32), out1.tracklets_numpy(n)["param"].view(np.uint32))
+    bad_x = b.x.copy()
+    bad_x[len(bad_x) // 2] += 0.5
+    wrong = DeviceHits(b.y, b.z, b.row, b.hit_offset, x=bad_x)
+    tr.track(wrong, tr.output(wrong))
+    with pytest.raises(C.CatpcError) as e:
+        tr.result()
+    assert e.value.status == C.CATPC_E_INVALID and "row_x" in str(e.value)
