@@ -66,12 +66,19 @@ def lib():
             getattr(L, "oracle_spd" + sfx).argtypes = [vp]
         L.oracle_clean_links.argtypes = [i32, vp, vp, vp, vp, vp]
         L.oracle_select.argtypes = [i32, i32, i32, vp, vp, vp, i32, vp, vp, vp, vp]
+        L.oracle_fullfit_f32.argtypes = [i32, vp, i32, vp, vp, vp, ctypes.c_float, vp, i32, vp, vp, vp, vp, vp, vp,
+                                         vp]
+        L.oracle_fullfit_f64.argtypes = [i32, vp, i32, vp, vp, vp, ctypes.c_double, vp, i32, vp, vp, vp, vp, vp,
+                                         vp, vp]
+        L.oracle_fullfit_transport_f32.argtypes = [vp, vp, vp, ctypes.c_float, vp]
+        L.oracle_fullfit_transport_f64.argtypes = [vp, vp, vp, ctypes.c_double, vp]
         L.oracle_refit_mixed.argtypes = [i32, vp, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
         for f in ("oracle_neighbours_f32", "oracle_neighbours_f64", "oracle_tracklets_f32",
                   "oracle_tracklets_f64", "oracle_refit_f32", "oracle_refit_f64", "oracle_clean_links",
                   "oracle_refit_mixed", "oracle_init_f32", "oracle_init_f64", "oracle_propagate_f32",
                   "oracle_propagate_f64", "oracle_update_f32", "oracle_update_f64", "oracle_spd_f32",
-                  "oracle_spd_f64"):
+                  "oracle_spd_f64", "oracle_select", "oracle_fullfit_f32", "oracle_fullfit_f64",
+                  "oracle_fullfit_transport_f32", "oracle_fullfit_transport_f64"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -137,6 +144,42 @@ def select(n_hits, row_hit, n_hits_trk, flags, min_hits=10):
         pos += k
     assert len(tracks) == cnt[0] and pos == cnt[1]
     return owned, tracks
+
+
+def fullfit(row_x, rows, hy, hz, x_start, p_start, start_row, p=None, mode="f64"):
+    """Full Kalman refit of one track (oracle/fullfit.c): hits by ascending
+    row, start state at row start_row.  Returns dict x, param[5], cov[15]
+    (packed lower triangle over y, z, sin phi, tan lambda, q/pT), chi2, ndf,
+    flags, at the outermost hit."""
+    p = p or Params()
+    real = np.float32 if mode == "f32" else np.float64
+    rx = _c(row_x, np.float32)
+    rows, hy, hz = _c(rows, np.int32), _c(hy, np.float32), _c(hz, np.float32)
+    ps = _c(p_start, real)
+    x = np.zeros(1, real)
+    par = np.zeros(5, real)
+    cov = np.zeros(15, real)
+    chi2 = np.zeros(1, real)
+    ndf = np.zeros(1, np.int32)
+    fl = np.zeros(1, np.int32)
+    cp = _cp(p)
+    fn = lib().oracle_fullfit_f32 if mode == "f32" else lib().oracle_fullfit_f64
+    fn(len(rx), rx.ctypes.data, len(rows), rows.ctypes.data, hy.ctypes.data, hz.ctypes.data, real(x_start),
+       ps.ctypes.data, int(start_row), ctypes.byref(cp), x.ctypes.data, par.ctypes.data, cov.ctypes.data,
+       chi2.ctypes.data, ndf.ctypes.data, fl.ctypes.data)
+    return {"x": x[0], "param": par, "cov": cov, "chi2": chi2[0], "ndf": int(ndf[0]), "flags": int(fl[0])}
+
+
+def fullfit_transport(x, param, cov, x1, p=None, mode="f64"):
+    """One transport step of the refit: returns (x, param, cov, rc)."""
+    p = p or Params()
+    real = np.float32 if mode == "f32" else np.float64
+    xx = np.array([x], real)
+    pp = np.array(param, real)
+    cc = np.array(cov, real)
+    fn = lib().oracle_fullfit_transport_f32 if mode == "f32" else lib().oracle_fullfit_transport_f64
+    rc = fn(xx.ctypes.data, pp.ctypes.data, cc.ctypes.data, real(x1), ctypes.byref(_cp(p)))
+    return xx[0], pp, cc, rc
 
 
 def _trk_out(m, n_rows, real):

@@ -22,7 +22,9 @@ def build(force: bool = True) -> str:
                  ("tracker.c", [], "tracker_f64.o"),
                  ("links.c", [], "links.o"),
                  ("refit_mixed.c", [], "refit_mixed.o"),
-                 ("select.c", [], "select.o")]
+                 ("select.c", [], "select.o"),
+                 ("fullfit.c", ["-DORACLE_F32"], "fullfit_f32.o"),
+                 ("fullfit.c", [], "fullfit_f64.o")]
         for src, defs, obj in units:
             o = os.path.join(tmp, obj)
             subprocess.run(["gcc", *CFLAGS, *defs, "-c", os.path.join(HERE, src), "-o", o], check=True)

@@ -81,4 +81,22 @@ int32_t oracle_select(int32_t n_hits, int32_t n_rows, int32_t n_trk, const int32
                       const int32_t* trk_n_hits, const int32_t* flags, int32_t min_hits,
                       int32_t* owned, int32_t* track_hits, int32_t* n_tracks, int32_t* n_track_hits);
 
+/* Full Kalman refit of one track (fullfit.c), both builds.  rows/hy/hz: the
+ * track's hits by ascending row; (x_start, p_start) the start state at
+ * row start_row.  Outputs at the outermost hit: x, p[5], packed covariance
+ * C[15] over (y, z, sin phi, tan lambda, q/pT), chi^2, ndf = 2 hits - 5,
+ * flags: 1 done, 2 |sin phi| limit, 4 arc-length limit, 8 innovation
+ * covariance not positive, 64 bad input. */
+#define ORACLE_FULLFIT_DECL(SFX, REAL)                                                                   \
+  int32_t oracle_fullfit##SFX(int32_t n_rows, const float* row_x, int32_t n, const int32_t* rows,        \
+                              const float* hy, const float* hz, REAL x_start, const REAL* p_start,       \
+                              int32_t start_row, const oracle_params* prm, REAL* x_out, REAL* p_out,      \
+                              REAL* C_out, REAL* chi2_out, int32_t* ndf_out, int32_t* flags_out);
+ORACLE_FULLFIT_DECL(_f32, float)
+ORACLE_FULLFIT_DECL(_f64, double)
+/* One transport step of the refit (state x, p[5], packed C[15]) to x1:
+ * returns 0, 2 or 4 as the transport of the tracklet filter. */
+int32_t oracle_fullfit_transport_f32(float* x, float* p, float* C, float x1, const oracle_params* prm);
+int32_t oracle_fullfit_transport_f64(double* x, double* p, double* C, double x1, const oracle_params* prm);
+
 #endif
