@@ -138,6 +138,21 @@ typedef struct {
   int64_t hit_capacity;
 } catpc_tracks;
 
+/* Refitted tracks (caller-owned device memory), one entry per selected track,
+ * at the track's outermost hit: x, parameters (y, z, sin phi, tan lambda,
+ * q/pT), packed lower-triangle covariance over the same order, chi^2, ndf =
+ * 2 hits - 5, flags (1 done; 2 |sin phi| limit; 4 arc-length limit; 8
+ * innovation covariance not positive; 64 inconsistent track record). */
+typedef struct {
+  float* x;        /* device [capacity] */
+  float* param;    /* device [capacity][5] */
+  float* cov;      /* device [capacity][15] */
+  float* chi2;     /* device [capacity] */
+  int32_t* ndf;    /* device [capacity] */
+  int32_t* flags;  /* device [capacity] */
+  int64_t capacity;
+} catpc_fits;
+
 typedef struct catpc_ctx catpc_ctx;
 
 /* Defaults of the method parameters and of the tuning. */
@@ -228,6 +243,19 @@ catpc_status catpc_fp32_probe(int32_t op, const float* a, const float* b, float*
  * missing or misaligned arrays. */
 catpc_status catpc_select_tracklets(catpc_ctx* ctx, const catpc_input* in, const catpc_output* trk,
                                     const catpc_tracks* out, void* stream);
+
+/* Full Kalman refit of the selected tracks (Sec. 2 item 4: the final fit
+ * uses the full Kalman filter; constant field here).  Per track: the
+ * tracklet's parameters carried row by row to the innermost hit, prior
+ * covariance diag(sigma_y^2, sigma_z^2, 1, 1, 100), then row by row outward:
+ * helix transport of the state, C <- F C F^T with the full first-order
+ * Jacobian (z coupled to sin phi and q/pT), a 2-d Kalman update at each of
+ * the track's hits; result at the outermost hit.  Reads `trk` (x_ref, param,
+ * first_row, tracklet_offset) and `tracks` from a finished selection.
+ * Requires out->capacity >= tracks->track_capacity (CATPC_E_INVALID
+ * otherwise).  Asynchronous on `stream`. */
+catpc_status catpc_refit_tracks(catpc_ctx* ctx, const catpc_input* in, const catpc_output* trk,
+                                const catpc_tracks* tracks, const catpc_fits* out, void* stream);
 
 /* Synchronise `stream` and report the last selection: the number of tracks
  * and of their hits.  CATPC_E_CAPACITY if the output held fewer, or if the

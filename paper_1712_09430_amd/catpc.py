@@ -24,7 +24,7 @@ STAGES = ("row_index", "grid", "neighbours", "clean_start", "scan", "compact", "
 
 EXPORTS = ("catpc_stage_times", "catpc_work_counts", "catpc_default_params", "catpc_default_tuning", "catpc_row_stride", "catpc_workspace_bytes", "catpc_create", "catpc_destroy",
            "catpc_set_params", "catpc_set_tuning", "catpc_get_tuning", "catpc_track_batch", "catpc_track_plain",
-           "catpc_result", "catpc_fetch_tracklets", "catpc_select_tracklets", "catpc_select_result", "catpc_fp32_probe", "catpc_probe_copy", "catpc_probe_fma",
+           "catpc_result", "catpc_fetch_tracklets", "catpc_select_tracklets", "catpc_select_result", "catpc_refit_tracks", "catpc_fp32_probe", "catpc_probe_copy", "catpc_probe_fma",
            "catpc_last_error")
 
 
@@ -61,6 +61,11 @@ class catpc_output(ctypes.Structure):
                 ("tracklet_offset", _vp), ("tracklet_capacity", ctypes.c_int64), ("x_ref", _vp), ("param", _vp),
                 ("cov", _vp), ("row_hit", _vp), ("start_row", _vp), ("first_row", _vp), ("last_row", _vp),
                 ("n_hits", _vp), ("flags", _vp)]
+
+
+class catpc_fits(ctypes.Structure):
+    _fields_ = [("x", _vp), ("param", _vp), ("cov", _vp), ("chi2", _vp), ("ndf", _vp), ("flags", _vp),
+                ("capacity", ctypes.c_int64)]
 
 
 class catpc_tracks(ctypes.Structure):
@@ -108,6 +113,8 @@ def lib():
         L.catpc_select_tracklets.argtypes = [_vp, P(catpc_input), P(catpc_output), P(catpc_tracks), _vp]
         L.catpc_select_tracklets.restype = st
         L.catpc_select_result.argtypes = [_vp, _vp, P(ctypes.c_int64), P(ctypes.c_int64)]
+        L.catpc_refit_tracks.argtypes = [_vp, P(catpc_input), P(catpc_output), P(catpc_tracks), P(catpc_fits), _vp]
+        L.catpc_refit_tracks.restype = st
         L.catpc_select_result.restype = st
         L.catpc_stage_times.argtypes = [_vp, P(catpc_input), P(catpc_output), _vp, _vp]
         L.catpc_stage_times.restype = st
@@ -204,6 +211,11 @@ def catpc_fetch_tracklets(ctx, inp, first, out, stream):
 def catpc_select_tracklets(ctx, inp, trk, tracks, stream):
     return _check(lib().catpc_select_tracklets(ctx, ctypes.byref(inp), ctypes.byref(trk), ctypes.byref(tracks),
                                                stream))
+
+
+def catpc_refit_tracks(ctx, inp, trk, tracks, fits, stream):
+    return _check(lib().catpc_refit_tracks(ctx, ctypes.byref(inp), ctypes.byref(trk), ctypes.byref(tracks),
+                                           ctypes.byref(fits), stream))
 
 
 def catpc_select_result(ctx, stream):

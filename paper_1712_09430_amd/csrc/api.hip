@@ -139,6 +139,7 @@ Consts make_consts(const catpc_params& p) {
   c.min_hits = p.min_hits;
   c.precision = p.precision;
   c.sy2d = (double)p.sigma_y * (double)p.sigma_y;
+  c.kbd = -0.00299792458 * (double)p.bz;
   c.sz2d = (double)p.sigma_z * (double)p.sigma_z;
   return c;
 }
@@ -706,6 +707,52 @@ catpc_status catpc_select_tracklets(catpc_ctx* ctx, const catpc_input* in, const
   if (rc) return rc;
   ctx->sel_out = *out;
   ctx->have_sel = true;
+  return CATPC_OK;
+}
+
+catpc_status catpc_refit_tracks(catpc_ctx* ctx, const catpc_input* in, const catpc_output* trk,
+                                const catpc_tracks* tracks, const catpc_fits* out, void* stream) {
+  if (!ctx || !in || !trk || !tracks || !out) return fail(CATPC_E_INVALID, "NULL argument");
+  if (in->n_sectors < 0 || in->n_sectors > ctx->max_sectors || in->n_hits < 0 || in->n_hits > ctx->max_hits)
+    return fail(CATPC_E_INVALID, "sizes beyond the context's maxima");
+  if (in->n_sectors > 0 && (!in->hit_offset || (in->n_hits > 0 && (!in->y || !in->z || !in->row))))
+    return fail(CATPC_E_INVALID, "hit arrays are NULL");
+  if (!trk->tracklet_offset || trk->tracklet_capacity < 0 ||
+      (trk->tracklet_capacity > 0 && (!trk->x_ref || !trk->param || !trk->first_row)))
+    return fail(CATPC_E_INVALID, "tracklet arrays are NULL");
+  if (!tracks->track_offset || tracks->track_capacity < 0 || tracks->hit_capacity < 0 ||
+      (tracks->track_capacity > 0 && (!tracks->track_tracklet || !tracks->track_n_hits || !tracks->track_hit_offset)) ||
+      (tracks->hit_capacity > 0 && !tracks->track_hits))
+    return fail(CATPC_E_INVALID, "track arrays are NULL");
+  if (out->capacity < tracks->track_capacity) return fail(CATPC_E_INVALID, "fit capacity below track capacity");
+  if (out->capacity > 0 && (!out->x || !out->param || !out->cov || !out->chi2 || !out->ndf || !out->flags))
+    return fail(CATPC_E_INVALID, "fit arrays are NULL");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (in->n_sectors == 0 || out->capacity == 0) return CATPC_OK;
+  TrackletOut T{};
+  T.x_ref = trk->x_ref;
+  T.param = trk->param;
+  T.first_row = trk->first_row;
+  TracksOut R;
+  R.track_offset = tracks->track_offset;
+  R.track_tracklet = tracks->track_tracklet;
+  R.track_n_hits = tracks->track_n_hits;
+  R.track_hit_offset = tracks->track_hit_offset;
+  R.track_capacity = tracks->track_capacity;
+  R.track_hits = tracks->track_hits;
+  R.hit_capacity = tracks->hit_capacity;
+  FitsOut F;
+  F.x = out->x;
+  F.param = out->param;
+  F.cov = out->cov;
+  F.chi2 = out->chi2;
+  F.ndf = out->ndf;
+  F.flags = out->flags;
+  F.capacity = out->capacity;
+  const int64_t lanes = std::min<int64_t>(out->capacity, (int64_t)ctx->n_cu * 4 * 256);
+  HIP_TRY(launch_fullfit(inputs_of(in), in->n_sectors, ctx->n_rows, ctx->row_x, ctx->consts, trk->tracklet_offset,
+                         T, trk->tracklet_capacity, R, F, ctx->ws, (int)((lanes + 255) / 256), st));
   return CATPC_OK;
 }
 

@@ -45,6 +45,7 @@ struct Consts {
   int32_t min_hits;
   int32_t precision;
   double sy2d, sz2d; // cluster variances for the binary64-covariance refit
+  double kbd;        // kb in binary64 for the full refit
 };
 
 struct Workspace {
@@ -71,7 +72,8 @@ constexpr int kXcds = 8;         // MI355X: 8 accelerator dies, workgroups dispa
 constexpr int kCtrWork = 0;      // [0, kXcds): work counters of the tracklet kernel, one per slot partition
 constexpr int kCtrError = 8;     // bit 0: invalid rows seen; bit 1: selection saw only part of the tracklets;
                                  // bit 2: a tracklet record names a hit outside its sector; bit 3: x differs
-                                 // from the row planes; bit 4: too many tracklets in a sector for the selection
+                                 // from the row planes; bit 4: too many tracklets in a sector for the selection;
+                                 // bit 5: more tracks than the refit output holds
 constexpr int kCtrCounts = 9;    // [9, 13): transports, updates, gated candidates, row searches
 constexpr int kCtrSelTracks = 13;  // selected tracks
 constexpr int kCtrSelHits = 14;    // hits they keep
@@ -99,6 +101,16 @@ struct TracksOut {
   int64_t track_capacity;
   int32_t* track_hits;
   int64_t hit_capacity;
+};
+
+struct FitsOut {
+  float* x;
+  float* param;
+  float* cov;
+  float* chi2;
+  int32_t* ndf;
+  int32_t* flags;
+  int64_t capacity;
 };
 
 struct TrackletOut {
@@ -141,6 +153,9 @@ hipError_t launch_tracklets(const Inputs& in, Span sp, int n_rows, const float* 
 hipError_t launch_select(const Inputs& in, int S, const int64_t* toff, int64_t cap, int64_t max_slots, int n_rows,
                          const TrackletOut& trk, const Consts& c, const Workspace& ws, const TracksOut& out,
                          int64_t n_hits, int grid, hipStream_t st);
+hipError_t launch_fullfit(const Inputs& in, int S, int n_rows, const float* row_x, const Consts& c,
+                          const int64_t* toff, const TrackletOut& trk, int64_t trk_cap, const TracksOut& tr,
+                          const FitsOut& out, const Workspace& ws, int grid, hipStream_t st);
 hipError_t launch_refit64(const Inputs& in, Span sp, int n_rows, const float* row_x, const Consts& c,
                           const Workspace& ws, const int64_t* toff, int64_t first, int64_t cap,
                           const TrackletOut& out, int grid, hipStream_t st);

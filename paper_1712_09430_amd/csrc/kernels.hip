@@ -1258,6 +1258,204 @@ __global__ __launch_bounds__(256) void k_sel_emit(Inputs in, int S, const int64_
   }
 }
 
+// ------------------------------------------------------ full Kalman refit
+// Sec. 2 item 4: the final fit with the full Kalman filter, here of each
+// selected track: full 5x5 covariance over (y, z, sin phi, tan lambda, q/pT),
+// the tracklet filter's helix transport of the state, covariance C <- F C F^T
+// with the first-order Jacobian including the terms that couple z to
+// (sin phi, q/pT), 2-d updates with (y, z); start from the tracklet's
+// parameters carried to the innermost hit, prior diag(sy^2, sz^2, 1, 1, 100);
+// result at the outermost hit.  One lane per track, in binary64 (MI355X runs
+// binary64 vector arithmetic at the binary32 rate; in binary32 the long
+// coupled covariance products lose about 1e-3 cm in z and 1e-3 in q/pT).
+// The matrix products run over every index (zeros included) in a fixed order.
+__device__ __forceinline__ int ff_tri(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
+
+struct FitJac {
+  double a, b, d, e, f, dS;  // dy/ds, dy/dq, ds/dq, dz/ds, dz/dq, dz/dl
+};
+
+__device__ __forceinline__ double ff_F(const FitJac& J, int i, int j) {
+  if (i == j) return 1.0;
+  if (i == 0 && j == 2) return J.a;
+  if (i == 0 && j == 4) return J.b;
+  if (i == 1 && j == 2) return J.e;
+  if (i == 1 && j == 3) return J.dS;
+  if (i == 1 && j == 4) return J.f;
+  if (i == 2 && j == 4) return J.d;
+  return 0.0;
+}
+
+// State transport to x1 (the tracklet filter's formulas) and the Jacobian.
+__device__ __forceinline__ int ff_transport(double& x, double* p, double x1, double kb, FitJac* J) {
+  const double dx = x1 - x;
+  const double k = kb * p[4];
+  const double s0 = p[2];
+  const double s1 = s0 + k * dx;
+  if (!(fabs(s1) < 0.999)) return 2;
+  const double c0 = sqrt(1.0 - s0 * s0);
+  const double c1 = sqrt(1.0 - s1 * s1);
+  const double T = (s0 + s1) / (c0 + c1);
+  const double dy = dx * T;
+  const double ch = sqrt(dx * dx + dy * dy);
+  const double u = (k * ch) * 0.5;
+  if (!(fabs(u) <= 0.2)) return 4;
+  const double u2 = u * u;
+  const double A = 1.0 + u2 * (1.0 / 6.0 + u2 * (3.0 / 40.0 + u2 * (5.0 / 112.0 + u2 * (35.0 / 1152.0))));
+  double dS = ch * A;
+  if (dx < 0.0) dS = -dS;
+  if (J) {
+    const double sm = (s0 + s1) * 0.5;
+    const double cm2 = 1.0 - sm * sm;
+    const double cm3 = cm2 * sqrt(cm2);
+    J->a = dx / cm3;
+    J->b = ((kb * dx) * dx * 0.5) / cm3;
+    J->d = kb * dx;
+    J->e = ((p[3] * dx) * sm) / cm3;
+    J->f = (J->e * J->d) * 0.5;
+    J->dS = dS;
+  }
+  x = x1;
+  p[0] = p[0] + dy;
+  p[1] = p[1] + p[3] * dS;
+  p[2] = s1;
+  return 0;
+}
+
+__device__ __forceinline__ void ff_transport_cov(double* C, const FitJac& J) {
+  double M[5][5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) acc = acc + ff_F(J, i, k) * C[ff_tri(k, j)];
+      M[i][j] = acc;
+    }
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) acc = acc + M[i][k] * ff_F(J, j, k);
+      C[ff_tri(i, j)] = acc;
+    }
+}
+
+__device__ __forceinline__ int ff_update(double* p, double* C, double my, double mz, double sy2, double sz2,
+                                         double& chi2) {
+  const double r0 = my - p[0];
+  const double r1 = mz - p[1];
+  const double S00 = C[ff_tri(0, 0)] + sy2;
+  const double S01 = C[ff_tri(1, 0)];
+  const double S11 = C[ff_tri(1, 1)] + sz2;
+  const double det = S00 * S11 - S01 * S01;
+  if (!(det > 0.0)) return 8;
+  const double i00 = S11 / det;
+  const double i01 = (0.0 - S01) / det;
+  const double i11 = S00 / det;
+  double K[5][2];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    K[i][0] = C[ff_tri(i, 0)] * i00 + C[ff_tri(i, 1)] * i01;
+    K[i][1] = C[ff_tri(i, 0)] * i01 + C[ff_tri(i, 1)] * i11;
+  }
+  const double s_new = p[2] + (K[2][0] * r0 + K[2][1] * r1);
+  if (!(fabs(s_new) < 0.999)) return 2;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) p[i] = p[i] + (K[i][0] * r0 + K[i][1] * r1);
+  double Cn[15];
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j)
+      Cn[ff_tri(i, j)] = C[ff_tri(i, j)] - (K[i][0] * C[ff_tri(0, j)] + K[i][1] * C[ff_tri(1, j)]);
+#pragma unroll
+  for (int q = 0; q < 15; ++q) C[q] = Cn[q];
+  chi2 = chi2 + (r0 * (i00 * r0 + i01 * r1) + r1 * (i01 * r0 + i11 * r1));
+  return 0;
+}
+
+__global__ __launch_bounds__(256) void k_fullfit(Inputs in, int S, int R, const float* __restrict__ row_x,
+                                                 Consts c, const int64_t* toff, TrackletOut trk, int64_t trk_cap,
+                                                 TracksOut tr, FitsOut out, Workspace ws) {
+  const int64_t n = min(tr.track_offset[S], min(tr.track_capacity, out.capacity));
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+    const int s = sector_of(tr.track_offset, 0, S, t);
+    const int64_t a = in.hit_offset[s];
+    const int32_t ns = (int32_t)(in.hit_offset[s + 1] - a);
+    const int64_t slot = toff[s] + tr.track_tracklet[t];
+    const int nh = tr.track_n_hits[t];
+    const int64_t h0 = tr.track_hit_offset[t];
+    double x = 0.0, p[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, C[15];
+#pragma unroll
+    for (int q = 0; q < 15; ++q) C[q] = 0.0;
+    double chi2 = 0.0;
+    int fl = 0, used = 0;
+    bool ok = nh > 0 && slot >= 0 && slot < trk_cap && h0 >= 0 && h0 + nh <= tr.hit_capacity;
+    int32_t h_first = 0, h_last = 0;
+    if (ok) {
+      h_first = tr.track_hits[h0];
+      h_last = tr.track_hits[h0 + nh - 1];
+      ok = h_first >= 0 && h_first < ns && h_last >= 0 && h_last < ns;
+    }
+    const int start_row = ok ? trk.first_row[slot] : 0;
+    const int r_first = ok ? in.row[a + h_first] : 0, r_last = ok ? in.row[a + h_last] : 0;
+    if (!ok || r_first < start_row || r_last >= R || start_row < 0) {
+      fl = 64;
+    } else {
+      x = (double)trk.x_ref[slot];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) p[i] = (double)trk.param[5 * slot + i];
+      for (int r = start_row + 1; r <= r_first && !fl; ++r)
+        fl = ff_transport(x, p, (double)row_x[r], c.kbd, nullptr);
+      if (!fl) {
+        C[ff_tri(0, 0)] = c.sy2d;
+        C[ff_tri(1, 1)] = c.sz2d;
+        C[ff_tri(2, 2)] = 1.0;
+        C[ff_tri(3, 3)] = 1.0;
+        C[ff_tri(4, 4)] = 100.0;
+        int k = 0;
+        int32_t hk = h_first;
+        int rk = r_first;
+        for (int r = r_first; r <= r_last; ++r) {
+          if (r > r_first) {
+            FitJac J;
+            fl = ff_transport(x, p, (double)row_x[r], c.kbd, &J);
+            if (fl) break;
+            ff_transport_cov(C, J);
+          }
+          if (k < nh && rk == r) {
+            fl = ff_update(p, C, (double)in.y[a + hk], (double)in.z[a + hk], c.sy2d, c.sz2d, chi2);
+            if (fl) break;
+            ++k;
+            ++used;
+            if (k < nh) {
+              hk = tr.track_hits[h0 + k];
+              if (hk < 0 || hk >= ns) { fl = 64; break; }
+              rk = in.row[a + hk];
+            }
+          }
+        }
+        if (!fl) fl = 1;
+      }
+    }
+    out.x[t] = (float)x;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) out.param[5 * t + i] = (float)p[i];
+#pragma unroll
+    for (int q = 0; q < 15; ++q) out.cov[15 * t + q] = (float)C[q];
+    out.chi2[t] = (float)chi2;
+    out.ndf[t] = 2 * used - 5;
+    out.flags[t] = fl;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && tr.track_offset[S] > min(tr.track_capacity, out.capacity))
+    atomicOr(&ws.counters[kCtrError], 32ull);
+}
+
 // ------------------------------------------------- binary64-covariance refit
 struct MTrk {
   float x, y, z, s, l, q;
@@ -1553,6 +1751,14 @@ hipError_t launch_select(const Inputs& in, int S, const int64_t* toff, int64_t c
   hipLaunchKernelGGL(k_sel_scan_local, dim3((unsigned)ng), dim3(kScanGroup), 0, st, toff, S, slots, ws);
   hipLaunchKernelGGL(k_sel_scan_top, dim3(1), dim3(1024), 0, st, ng, ws);
   hipLaunchKernelGGL(k_sel_emit, dim3(grid), dim3(256), 0, st, in, S, toff, slots, n_rows, trk, ws, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fullfit(const Inputs& in, int S, int n_rows, const float* row_x, const Consts& c,
+                          const int64_t* toff, const TrackletOut& trk, int64_t trk_cap, const TracksOut& tr,
+                          const FitsOut& out, const Workspace& ws, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_fullfit, dim3(grid), dim3(256), 0, st, in, S, n_rows, row_x, c, toff, trk, trk_cap, tr, out,
+                     ws);
   return hipGetLastError();
 }
 

@@ -122,6 +122,31 @@ class DeviceTracks:
                 "track_hits": self.track_hits[:n_track_hits].cpu().numpy()}
 
 
+class DeviceFits:
+    """Output buffers of the full refit: one entry per track slot."""
+
+    def __init__(self, capacity, device="cuda:0"):
+        dev = _need_gpu(device)
+        e = lambda shape, dt: torch.empty(shape, dtype=dt, device=dev)
+        self.capacity = int(capacity)
+        self.x = e(capacity, torch.float32)
+        self.param = e((capacity, 5), torch.float32)
+        self.cov = e((capacity, 15), torch.float32)
+        self.chi2 = e(capacity, torch.float32)
+        self.ndf = e(capacity, torch.int32)
+        self.flags = e(capacity, torch.int32)
+        s = C.catpc_fits()
+        for f in ("x", "param", "cov", "chi2", "ndf", "flags"):
+            setattr(s, f, _ptr(getattr(self, f)))
+        s.capacity = self.capacity
+        self.struct = s
+
+    def numpy(self, n):
+        g = lambda t: t[:n].cpu().numpy()
+        return {"x": g(self.x), "param": g(self.param), "cov": g(self.cov), "chi2": g(self.chi2),
+                "ndf": g(self.ndf), "flags": g(self.flags)}
+
+
 class Tracker:
     """One catpc context on one device."""
 
@@ -193,6 +218,15 @@ class Tracker:
         """Enqueue the tracklet selection of the last track call's output."""
         with torch.cuda.device(self.device):
             C.catpc_select_tracklets(self.ctx, hits.struct, out.struct, tracks.struct, _stream(self.device))
+
+    def fits_output(self, tracks):
+        """Refit buffers for every track slot of `tracks`."""
+        return DeviceFits(max(int(tracks.struct.track_capacity), 1), self.device)
+
+    def refit(self, hits, out, tracks, fits):
+        """Enqueue the full Kalman refit of the selected tracks."""
+        with torch.cuda.device(self.device):
+            C.catpc_refit_tracks(self.ctx, hits.struct, out.struct, tracks.struct, fits.struct, _stream(self.device))
 
     def select_result(self):
         """Synchronise; (n_tracks, n_track_hits)."""
