@@ -70,6 +70,7 @@ def lib():
                                          vp]
         L.oracle_fullfit_f64.argtypes = [i32, vp, i32, vp, vp, vp, ctypes.c_double, vp, i32, vp, vp, vp, vp, vp,
                                          vp, vp]
+        L.oracle_merge.argtypes = [i32, vp, vp, vp, i32] + [vp] * 11
         L.oracle_fullfit_transport_f32.argtypes = [vp, vp, vp, ctypes.c_float, vp]
         L.oracle_fullfit_transport_f64.argtypes = [vp, vp, vp, ctypes.c_double, vp]
         L.oracle_refit_mixed.argtypes = [i32, vp, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
@@ -78,7 +79,7 @@ def lib():
                   "oracle_refit_mixed", "oracle_init_f32", "oracle_init_f64", "oracle_propagate_f32",
                   "oracle_propagate_f64", "oracle_update_f32", "oracle_update_f64", "oracle_spd_f32",
                   "oracle_spd_f64", "oracle_select", "oracle_fullfit_f32", "oracle_fullfit_f64",
-                  "oracle_fullfit_transport_f32", "oracle_fullfit_transport_f64"):
+                  "oracle_fullfit_transport_f32", "oracle_fullfit_transport_f64", "oracle_merge"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -168,6 +169,36 @@ def fullfit(row_x, rows, hy, hz, x_start, p_start, start_row, p=None, mode="f64"
        ps.ctypes.data, int(start_row), ctypes.byref(cp), x.ctypes.data, par.ctypes.data, cov.ctypes.data,
        chi2.ctypes.data, ndf.ctypes.data, fl.ctypes.data)
     return {"x": x[0], "param": par, "cov": cov, "chi2": chi2[0], "ndf": int(ndf[0]), "flags": int(fl[0])}
+
+
+class _MP(ctypes.Structure):
+    _fields_ = [("max_gap", ctypes.c_int32), ("window", ctypes.c_float), ("chi2_max", ctypes.c_float)]
+
+
+@dataclasses.dataclass
+class MergeParams:
+    max_gap: int = 30
+    window: float = 10.0
+    chi2_max: float = 25.0
+
+
+def merge(row_x, ok, a_last, e_x, e_p, e_C, b_first, s_x, s_p, s_C, p=None, mp=None):
+    """Segment merging of one sector (oracle/merge.c): returns (next, chi2)."""
+    p = p or Params()
+    mp = mp or MergeParams()
+    n = len(ok)
+    rx = _c(row_x, np.float32)
+    arrs = [_c(ok, np.int32), _c(a_last, np.int32), _c(e_x, np.float32), _c(e_p, np.float32).reshape(-1),
+            _c(e_C, np.float32).reshape(-1), _c(b_first, np.int32), _c(s_x, np.float32),
+            _c(s_p, np.float32).reshape(-1), _c(s_C, np.float32).reshape(-1)]
+    for a, m in zip(arrs, (1, 1, 1, 5, 15, 1, 1, 5, 15)):
+        assert a.size == n * m
+    nxt = np.full(max(n, 1), -1, np.int32)
+    chi2 = np.full(max(n, 1), -1.0, np.float32)
+    lib().oracle_merge(len(rx), rx.ctypes.data, ctypes.byref(_cp(p)),
+                       ctypes.byref(_MP(int(mp.max_gap), float(mp.window), float(mp.chi2_max))), n,
+                       *[a.ctypes.data for a in arrs], nxt.ctypes.data, chi2.ctypes.data)
+    return nxt[:n], chi2[:n]
 
 
 def fullfit_transport(x, param, cov, x1, p=None, mode="f64"):

@@ -24,7 +24,8 @@ def build(force: bool = True) -> str:
                  ("refit_mixed.c", [], "refit_mixed.o"),
                  ("select.c", [], "select.o"),
                  ("fullfit.c", ["-DORACLE_F32"], "fullfit_f32.o"),
-                 ("fullfit.c", [], "fullfit_f64.o")]
+                 ("fullfit.c", [], "fullfit_f64.o"),
+                 ("merge.c", [], "merge.o")]
         for src, defs, obj in units:
             o = os.path.join(tmp, obj)
             subprocess.run(["gcc", *CFLAGS, *defs, "-c", os.path.join(HERE, src), "-o", o], check=True)

@@ -99,4 +99,20 @@ ORACLE_FULLFIT_DECL(_f64, double)
 int32_t oracle_fullfit_transport_f32(float* x, float* p, float* C, float x1, const oracle_params* prm);
 int32_t oracle_fullfit_transport_f64(double* x, double* p, double* C, double x1, const oracle_params* prm);
 
+/* Merging of track segments of one sector across row gaps (merge.c), binary64.
+ * Per track: ok (refit done), a_last (row of its outermost hit), end state
+ * e_x, e_p[5], e_C[15] (the refit result), b_first (its tracklet's first
+ * row), start state s_x, s_p[5], s_C[15] (the tracklet's state at x_ref).
+ * Output: next[a] = the track that continues track a, or -1, and the chi^2
+ * of that link rounded to binary32, else -1. */
+typedef struct {
+  int32_t max_gap; /* B's first row at most this many rows above A's last */
+  float window;    /* cm, straight-line window in y and z */
+  float chi2_max;  /* cut on the 5-parameter chi^2 */
+} oracle_merge_params;
+int32_t oracle_merge(int32_t n_rows, const float* row_x, const oracle_params* prm, const oracle_merge_params* mp,
+                     int32_t n, const int32_t* ok, const int32_t* a_last, const float* e_x, const float* e_p,
+                     const float* e_C, const int32_t* b_first, const float* s_x, const float* s_p, const float* s_C,
+                     int32_t* next, float* chi2_out);
+
 #endif

@@ -41,7 +41,7 @@ class _Cfg(ctypes.Structure):
                 ("eta_min", ctypes.c_double), ("eta_max", ctypes.c_double),
                 ("phi_min", ctypes.c_double), ("phi_max", ctypes.c_double),
                 ("sector_first", ctypes.c_int32), ("sector_count", ctypes.c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("dead_first", ctypes.c_int32), ("dead_count", ctypes.c_int32)]
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -110,7 +110,7 @@ def helix_point(q_over_pt, tanl, phi0, bz, alpha, path):
 
 
 def _cfg(seed, sectors, n_rows=N_ROWS, bz=BZ, sigma=0.1, noise_frac=0.1, pt=(0.2, 10.0),
-         eta=(-0.9, 0.9), phi=(0.0, 2 * math.pi)):
+         eta=(-0.9, 0.9), phi=(0.0, 2 * math.pi), dead_rows=(0, 0)):
     c = _Cfg()
     c.n_rows = n_rows
     c.x_first, c.x_last = X_FIRST, X_LAST
@@ -121,6 +121,7 @@ def _cfg(seed, sectors, n_rows=N_ROWS, bz=BZ, sigma=0.1, noise_frac=0.1, pt=(0.2
     c.phi_min, c.phi_max = phi
     c.sector_first, c.sector_count = sectors
     c.seed = seed
+    c.dead_first, c.dead_count = dead_rows
     return c
 
 

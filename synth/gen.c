@@ -82,6 +82,7 @@ typedef struct {
   double phi_min, phi_max; /* rad, uniform */
   int32_t sector_first, sector_count; /* sectors read out */
   uint64_t seed;
+  int32_t dead_first, dead_count;     /* pad rows [first, first + count) read out nothing */
 } synth_cfg;
 
 typedef struct {
@@ -214,6 +215,7 @@ synth_event* synth_generate_tracks(const synth_cfg* cfg, int32_t n_tracks, const
         if (fabs(yl) > xr * cfg->tan_half_open) continue;
         if (fabs(zl) > cfg->z_max) continue;
         if (sideA ? zl < 0.0 : zl >= 0.0) continue;
+        if (r >= cfg->dead_first && r < cfg->dead_first + cfg->dead_count) continue;
         const u32x4 g = draw(cfg->seed, event_id, (uint32_t)t, (uint32_t)s, (uint32_t)r, ST_SMEAR);
         const double u1 = unif(g.v[0]), u2 = unif(g.v[1]);
         const double rad = sqrt(-2.0 * log(u1));
@@ -236,6 +238,7 @@ synth_event* synth_generate_tracks(const synth_cfg* cfg, int32_t n_tracks, const
       const u32x4 g = draw(cfg->seed, event_id, (uint32_t)m, (uint32_t)s, 0, ST_NOISE);
       int r = (int)(unif(g.v[0]) * nr);
       if (r >= nr) r = nr - 1;
+      if (r >= cfg->dead_first && r < cfg->dead_first + cfg->dead_count) continue;
       const double xr = (double)rx[r];
       const double yl = (2.0 * unif(g.v[1]) - 1.0) * xr * cfg->tan_half_open;
       double zl = unif(g.v[2]) * cfg->z_max;

@@ -64,3 +64,47 @@ def compare_sector(batch, s, g, params, mode="f32"):
                 diff = f"shape {a.shape} vs {b.shape}"
             bad.append(f"sector {s}: tracklet field {k} differs at tracklets {diff}")
     return bad
+
+
+def oracle_merge_sector(batch, s, P, mp=None):
+    """The oracle's own chain on sector s (tracklets, selection, binary64
+    refit rounded to binary32 as the refit output stores it, merging).
+    Returns (next, chi2, labels) with sector-local track indices; labels =
+    the most frequent generator label of each track's hits."""
+    sec = batch.sector(s)
+    o = oracle.track_sector(sec["y"], sec["z"], sec["row"], batch.row_x, P, "f32")
+    _, want = oracle.select(len(sec["y"]), o["row_hit"], o["n_hits"], o["flags"], P.min_hits)
+    n = len(want)
+    ok = np.zeros(n, np.int32)
+    a_last = np.zeros(n, np.int32)
+    b_first = np.zeros(n, np.int32)
+    e_x, s_x = np.zeros(n, np.float32), np.zeros(n, np.float32)
+    e_p, s_p = np.zeros((n, 5), np.float32), np.zeros((n, 5), np.float32)
+    e_C, s_C = np.zeros((n, 15), np.float32), np.zeros((n, 15), np.float32)
+    labels = np.full(n, -1, np.int64)
+    for k, (t, hits) in enumerate(want):
+        r = oracle.fullfit(batch.row_x, sec["row"][hits], sec["y"][hits], sec["z"][hits], o["x_ref"][t],
+                           o["param"][t], o["first_row"][t], P, mode="f64")
+        ok[k] = r["flags"] == 1
+        a_last[k] = sec["row"][hits[-1]]
+        e_x[k], e_p[k], e_C[k] = r["x"], r["param"], r["cov"]
+        b_first[k], s_x[k], s_p[k], s_C[k] = o["first_row"][t], o["x_ref"][t], o["param"][t], o["cov"][t]
+        if "label" in sec:
+            v, c = np.unique(sec["label"][hits], return_counts=True)
+            labels[k] = v[np.argmax(c)]
+    nxt, chi2 = oracle.merge(batch.row_x, ok, a_last, e_x, e_p, e_C, b_first, s_x, s_p, s_C, P, mp)
+    return nxt, chi2, labels
+
+
+def chains(nxt):
+    """prev and head of every segment from the next links (plain walk)."""
+    n = len(nxt)
+    prev = np.full(n, -1, np.int32)
+    for a in range(n):
+        if nxt[a] >= 0:
+            prev[nxt[a]] = a
+    head = np.arange(n, dtype=np.int32)
+    for a in range(n):
+        while prev[head[a]] >= 0:
+            head[a] = prev[head[a]]
+    return prev, head
