@@ -63,6 +63,28 @@ def profiled_traffic(workload_name, tuning):
     return rec["per_launch"]
 
 
+DEAD_BAND = (70, 8)  # pad rows without clusters in the merging leg's second batch
+
+
+def merge_leg(tr, hits, out, tracks, fits, n_tracks, stream, reps=5):
+    """Time the segment merging (HIP events on `stream`) and count its links."""
+    import torch
+    merges = tr.merges_output(tracks)
+    tr.merge(hits, out, tracks, fits, merges)
+    torch.cuda.synchronize()
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record(stream)
+    for _ in range(reps):
+        tr.merge(hits, out, tracks, fits, merges)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    mn = merges.numpy(n_tracks)
+    return {"ms": s0.elapsed_time(s1) / reps, "tracks": int(n_tracks), "links": int(np.sum(mn["next"] >= 0)),
+            "chains": int(np.sum((mn["next"] >= 0) & (mn["prev"] < 0))),
+            "what": "segment merging inside each sector: straight-line window, transported 5x5 covariance, "
+                    "chi^2 of the two states, mutual best link (binary64)"}
+
+
 def workload(name, seed):
     import synth
     if name == "batch64":
@@ -258,6 +280,8 @@ def main():
     ap.add_argument("--no-peaks", action="store_true", help="skip the copy and FMA peak probes")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision-form report")
     ap.add_argument("--no-scheduling", action="store_true", help="skip the scheduling baselines")
+    ap.add_argument("--no-dead-band", action="store_true",
+                    help="skip the merging leg's second batch (same events, 8 dead pad rows)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", default="auto",
                     help="'auto' (the autotuner's cache for this architecture, if present), 'default', or a JSON "
@@ -381,7 +405,32 @@ def main():
              "what": "full Kalman refit of the selected tracks: 5x5 covariance, coupled Jacobian, binary64"}
     log(f"[bench] refit: {refit['ms']:.3f} ms, {refit['done']} of {n_tracks} tracks, "
         f"chi2/ndf {refit['chi2_per_ndf_mean']}")
+    # segment merging inside the sectors (after the refit)
+    merge = merge_leg(tr, hits, out, tracks, fits, n_tracks, stream)
+    log(f"[bench] merge: {merge['ms']:.3f} ms, {merge['links']} links among {n_tracks} tracks")
     del tracks, fits
+    if not args.no_dead_band and args.workload == "batch64":
+        import synth
+        bd = synth.batch_workload(seed=args.seed, n_events=64, dead_rows=DEAD_BAND)
+        hd = DeviceHits(bd.y, bd.z, bd.row, bd.hit_offset, dev)
+        od = tr.output(hd)
+        tr.track(hd, od)
+        st_d, _ = tr.result()
+        if st_d != C.CATPC_OK:
+            raise SystemExit(f"catpc status {st_d}: {C.catpc_last_error()}")
+        td = tr.tracks_output(hd, od)
+        tr.select(hd, od, td)
+        nt_d, _ = tr.select_result()
+        fd = tr.fits_output(td)
+        tr.refit(hd, od, td, fd)
+        merge["dead_band"] = merge_leg(tr, hd, od, td, fd, nt_d, stream)
+        merge["dead_band"]["rows"] = [DEAD_BAND[0], DEAD_BAND[0] + DEAD_BAND[1] - 1]
+        merge["dead_band"]["hits"] = int(hd.n_hits)
+        log(f"[bench] merge, dead rows {DEAD_BAND[0]}-{DEAD_BAND[0] + DEAD_BAND[1] - 1}: "
+            f"{merge['dead_band']['ms']:.3f} ms, {merge['dead_band']['links']} links among {nt_d} tracks")
+        del bd, hd, od, td, fd
+        tr.track(hits, out)  # leave the context's last call on the main workload
+        tr.result()
 
     flops = (work[0] * FLOPS_PER_TRANSPORT + work[1] * FLOPS_PER_UPDATE + work[3] * FLOPS_PER_SEARCH +
              work[2] * FLOPS_PER_CANDIDATE)
@@ -473,7 +522,7 @@ def main():
            "plain": plain, "batched_over_plain": (value / plain["hits_per_s"]) if plain else None,
            "serving": serving, "stages_ms": stages, "roofline": {k: v for k, v in dominant.items() if k != "kernel"} |
            {"kernel": dominant["kernel"]}, "rooflines": {"k_tracklets": rl_tc, "k_neighbours": rl_nf},
-           "selection": sel, "refit": refit, "scheduling": scheduling, "achievable_peaks": peaks, "precision": precision, "cpu_baseline": cpu}
+           "selection": sel, "refit": refit, "merge": merge, "scheduling": scheduling, "achievable_peaks": peaks, "precision": precision, "cpu_baseline": cpu}
     print(json.dumps(res), flush=True)
 
 

@@ -153,11 +153,32 @@ typedef struct {
   int64_t capacity;
 } catpc_fits;
 
+/* Cuts of the segment merging (catpc_merge_tracks). */
+typedef struct {
+  int32_t max_gap;  /* a continuation starts 1 .. max_gap rows above the segment's outermost hit (30) */
+  float window;     /* cm: straight-line window in y and z at the continuation's start (10) */
+  float chi2_max;   /* cut on the 5-parameter chi^2 of the two states (25) */
+} catpc_merge_params;
+
+/* Merged segments (caller-owned device memory), one entry per selected
+ * track: next = the track that continues it (same sector, further out), or
+ * -1; prev = the track it continues, or -1; head = the first segment of its
+ * chain (itself when prev is -1), so the tracks of one chain share head;
+ * chi2 = the chi^2 of the link to next, or -1. */
+typedef struct {
+  int32_t* next;  /* device [capacity] */
+  int32_t* prev;  /* device [capacity] */
+  int32_t* head;  /* device [capacity] */
+  float* chi2;    /* device [capacity] */
+  int64_t capacity;
+} catpc_merges;
+
 typedef struct catpc_ctx catpc_ctx;
 
 /* Defaults of the method parameters and of the tuning. */
 void catpc_default_params(catpc_params* p);
 void catpc_default_tuning(catpc_tuning* t);
+void catpc_default_merge_params(catpc_merge_params* m);
 
 /* Row stride of the hit-per-row output: n_rows rounded up to a multiple of 8
  * (each tracklet's record is written in aligned 32-byte chunks). */
@@ -256,6 +277,34 @@ catpc_status catpc_select_tracklets(catpc_ctx* ctx, const catpc_input* in, const
  * otherwise).  Asynchronous on `stream`. */
 catpc_status catpc_refit_tracks(catpc_ctx* ctx, const catpc_input* in, const catpc_output* trk,
                                 const catpc_tracks* tracks, const catpc_fits* out, void* stream);
+
+/* Merging of track segments inside each sector (Sec. 2 item 3: segments of
+ * one track that the following split, e.g. at a gap of rows without
+ * clusters, are merged before the tracks are merged across sector borders;
+ * that border step is not provided).  For a refitted track A (fit flags 1)
+ * and a refitted track B of the same sector whose tracklet starts 1 to
+ * max_gap rows above A's outermost hit:
+ *  - A's fitted state carried along a straight line to B's start x must land
+ *    within `window` of B's start state (the tracklet's state at x_ref) in y
+ *    and in z;
+ *  - A's state and covariance are carried row by row to B's first row with
+ *    the refit's helix transport and Jacobian (binary64);
+ *  - chi^2 = d^T (C_A + C_B)^-1 d over the five parameters, d = B's start
+ *    state - A's carried state, by Cholesky factorisation; the pair is
+ *    compatible when C_A + C_B is positive definite and chi^2 <= chi2_max.
+ * A's best continuation and B's best predecessor order by chi^2 rounded to
+ * binary32, ties to the smaller track index; A and B are linked when each is
+ * the other's best.  Deterministic (the best predecessor is a 64-bit atomic
+ * minimum of (chi^2, index), independent of the order of the atomics).
+ * Reads `trk` (x_ref, param, cov, first_row, tracklet_offset), `tracks`
+ * (with track_hits, for the outermost hit's row) and `fits` of the same
+ * selection; `mp` NULL takes the defaults.  Requires fits->capacity and
+ * out->capacity >= tracks->track_capacity (CATPC_E_INVALID otherwise);
+ * CATPC_E_INVALID for max_gap outside [1, 4096] or negative cuts.
+ * Asynchronous on `stream`. */
+catpc_status catpc_merge_tracks(catpc_ctx* ctx, const catpc_input* in, const catpc_output* trk,
+                                const catpc_tracks* tracks, const catpc_fits* fits, const catpc_merge_params* mp,
+                                const catpc_merges* out, void* stream);
 
 /* Synchronise `stream` and report the last selection: the number of tracks
  * and of their hits.  CATPC_E_CAPACITY if the output held fewer, or if the

@@ -24,7 +24,7 @@ STAGES = ("row_index", "grid", "neighbours", "clean_start", "scan", "compact", "
 
 EXPORTS = ("catpc_stage_times", "catpc_work_counts", "catpc_default_params", "catpc_default_tuning", "catpc_row_stride", "catpc_workspace_bytes", "catpc_create", "catpc_destroy",
            "catpc_set_params", "catpc_set_tuning", "catpc_get_tuning", "catpc_track_batch", "catpc_track_plain",
-           "catpc_result", "catpc_fetch_tracklets", "catpc_select_tracklets", "catpc_select_result", "catpc_refit_tracks", "catpc_fp32_probe", "catpc_probe_copy", "catpc_probe_fma",
+           "catpc_result", "catpc_fetch_tracklets", "catpc_select_tracklets", "catpc_select_result", "catpc_refit_tracks", "catpc_default_merge_params", "catpc_merge_tracks", "catpc_fp32_probe", "catpc_probe_copy", "catpc_probe_fma",
            "catpc_last_error")
 
 
@@ -66,6 +66,14 @@ class catpc_output(ctypes.Structure):
 class catpc_fits(ctypes.Structure):
     _fields_ = [("x", _vp), ("param", _vp), ("cov", _vp), ("chi2", _vp), ("ndf", _vp), ("flags", _vp),
                 ("capacity", ctypes.c_int64)]
+
+
+class catpc_merge_params(ctypes.Structure):
+    _fields_ = [("max_gap", ctypes.c_int32), ("window", ctypes.c_float), ("chi2_max", ctypes.c_float)]
+
+
+class catpc_merges(ctypes.Structure):
+    _fields_ = [("next", _vp), ("prev", _vp), ("head", _vp), ("chi2", _vp), ("capacity", ctypes.c_int64)]
 
 
 class catpc_tracks(ctypes.Structure):
@@ -115,6 +123,11 @@ def lib():
         L.catpc_select_result.argtypes = [_vp, _vp, P(ctypes.c_int64), P(ctypes.c_int64)]
         L.catpc_refit_tracks.argtypes = [_vp, P(catpc_input), P(catpc_output), P(catpc_tracks), P(catpc_fits), _vp]
         L.catpc_refit_tracks.restype = st
+        L.catpc_default_merge_params.argtypes = [P(catpc_merge_params)]
+        L.catpc_default_merge_params.restype = None
+        L.catpc_merge_tracks.argtypes = [_vp, P(catpc_input), P(catpc_output), P(catpc_tracks), P(catpc_fits),
+                                         P(catpc_merge_params), P(catpc_merges), _vp]
+        L.catpc_merge_tracks.restype = st
         L.catpc_select_result.restype = st
         L.catpc_stage_times.argtypes = [_vp, P(catpc_input), P(catpc_output), _vp, _vp]
         L.catpc_stage_times.restype = st
@@ -152,6 +165,12 @@ def catpc_default_tuning():
     t = catpc_tuning()
     lib().catpc_default_tuning(ctypes.byref(t))
     return t
+
+
+def catpc_default_merge_params():
+    m = catpc_merge_params()
+    lib().catpc_default_merge_params(ctypes.byref(m))
+    return m
 
 
 def catpc_row_stride(n_rows):
@@ -216,6 +235,12 @@ def catpc_select_tracklets(ctx, inp, trk, tracks, stream):
 def catpc_refit_tracks(ctx, inp, trk, tracks, fits, stream):
     return _check(lib().catpc_refit_tracks(ctx, ctypes.byref(inp), ctypes.byref(trk), ctypes.byref(tracks),
                                            ctypes.byref(fits), stream))
+
+
+def catpc_merge_tracks(ctx, inp, trk, tracks, fits, mp, out, stream):
+    return _check(lib().catpc_merge_tracks(ctx, ctypes.byref(inp), ctypes.byref(trk), ctypes.byref(tracks),
+                                           ctypes.byref(fits), None if mp is None else ctypes.byref(mp),
+                                           ctypes.byref(out), stream))
 
 
 def catpc_select_result(ctx, stream):

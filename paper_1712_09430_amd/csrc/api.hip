@@ -38,7 +38,7 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
   size_t row_first, hdr, bins, sorted, raw_up, raw_dn, mask, blk_cnt, blk_off, grp_off, start_glob, chain,
-      owner, sel_cnt, sel_loc, sel_grp, counters;
+      owner, sel_cnt, sel_loc, sel_grp, mrec, mkey, counters;
   size_t total;
 };
 
@@ -64,6 +64,8 @@ Layout plan(int32_t R, int64_t H, int32_t S) {
   L.sel_cnt = take(sizeof(int32_t) * slots);
   L.sel_loc = take(sizeof(int2) * slots);
   L.sel_grp = take(sizeof(longlong2) * (slots / 1024 + 8));
+  L.mrec = take(sizeof(float4) * slots);
+  L.mkey = take(sizeof(unsigned long long) * slots);
   L.counters = take(sizeof(unsigned long long) * kNumCounters);
   L.total = o;
   return L;
@@ -448,6 +450,8 @@ catpc_status catpc_create(int32_t n_rows, const float* row_x, const catpc_params
       w.sel_cnt = (int32_t*)(b + L.sel_cnt);
       w.sel_loc = (int2*)(b + L.sel_loc);
       w.sel_grp = (longlong2*)(b + L.sel_grp);
+      w.mrec = (float4*)(b + L.mrec);
+      w.mkey = (unsigned long long*)(b + L.mkey);
       w.counters = (unsigned long long*)(b + L.counters);
       e = hipMemset(w.counters, 0, sizeof(unsigned long long) * kNumCounters);
     }
@@ -753,6 +757,79 @@ catpc_status catpc_refit_tracks(catpc_ctx* ctx, const catpc_input* in, const cat
   const int64_t lanes = std::min<int64_t>(out->capacity, (int64_t)ctx->n_cu * 4 * 256);
   HIP_TRY(launch_fullfit(inputs_of(in), in->n_sectors, ctx->n_rows, ctx->row_x, ctx->consts, trk->tracklet_offset,
                          T, trk->tracklet_capacity, R, F, ctx->ws, (int)((lanes + 255) / 256), st));
+  return CATPC_OK;
+}
+
+void catpc_default_merge_params(catpc_merge_params* m) {
+  if (!m) return;
+  m->max_gap = 30;
+  m->window = 10.0f;
+  m->chi2_max = 25.0f;
+}
+
+catpc_status catpc_merge_tracks(catpc_ctx* ctx, const catpc_input* in, const catpc_output* trk,
+                                const catpc_tracks* tracks, const catpc_fits* fits, const catpc_merge_params* mp,
+                                const catpc_merges* out, void* stream) {
+  if (!ctx || !in || !trk || !tracks || !fits || !out) return fail(CATPC_E_INVALID, "NULL argument");
+  catpc_merge_params m;
+  catpc_default_merge_params(&m);
+  if (mp) m = *mp;
+  if (m.max_gap < 1 || m.max_gap > kMaxRows || !(m.window >= 0.0f) || !(m.chi2_max >= 0.0f))
+    return fail(CATPC_E_INVALID, "merge cuts: max_gap in [1, 4096], window and chi2_max >= 0");
+  if (in->n_sectors < 0 || in->n_sectors > ctx->max_sectors || in->n_hits < 0 || in->n_hits > ctx->max_hits)
+    return fail(CATPC_E_INVALID, "sizes beyond the context's maxima");
+  if (in->n_sectors > 0 && (!in->hit_offset || (in->n_hits > 0 && !in->row)))
+    return fail(CATPC_E_INVALID, "hit arrays are NULL");
+  if (!trk->tracklet_offset || trk->tracklet_capacity < 0 ||
+      (trk->tracklet_capacity > 0 && (!trk->x_ref || !trk->param || !trk->cov || !trk->first_row)))
+    return fail(CATPC_E_INVALID, "tracklet arrays are NULL");
+  if (!tracks->track_offset || tracks->track_capacity < 0 || tracks->hit_capacity < 0 ||
+      (tracks->track_capacity > 0 && (!tracks->track_tracklet || !tracks->track_n_hits || !tracks->track_hit_offset)) ||
+      (tracks->hit_capacity > 0 && !tracks->track_hits))
+    return fail(CATPC_E_INVALID, "track arrays are NULL");
+  if (fits->capacity < tracks->track_capacity || out->capacity < tracks->track_capacity)
+    return fail(CATPC_E_INVALID, "fit or merge capacity below track capacity");
+  if (fits->capacity > 0 && (!fits->x || !fits->param || !fits->cov || !fits->flags))
+    return fail(CATPC_E_INVALID, "fit arrays are NULL");
+  if (out->capacity > 0 && (!out->next || !out->prev || !out->head || !out->chi2))
+    return fail(CATPC_E_INVALID, "merge arrays are NULL");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (in->n_sectors == 0 || tracks->track_capacity == 0) return CATPC_OK;
+  TrackletOut T{};
+  T.x_ref = trk->x_ref;
+  T.param = trk->param;
+  T.cov = trk->cov;
+  T.first_row = trk->first_row;
+  TracksOut R;
+  R.track_offset = tracks->track_offset;
+  R.track_tracklet = tracks->track_tracklet;
+  R.track_n_hits = tracks->track_n_hits;
+  R.track_hit_offset = tracks->track_hit_offset;
+  R.track_capacity = tracks->track_capacity;
+  R.track_hits = tracks->track_hits;
+  R.hit_capacity = tracks->hit_capacity;
+  FitsOut F{};
+  F.x = fits->x;
+  F.param = fits->param;
+  F.cov = fits->cov;
+  F.flags = fits->flags;
+  F.capacity = fits->capacity;
+  MergeOut M;
+  M.next = out->next;
+  M.prev = out->prev;
+  M.head = out->head;
+  M.chi2 = out->chi2;
+  M.capacity = out->capacity;
+  MergeCuts cuts;
+  cuts.max_gap = m.max_gap;
+  cuts.window = (double)m.window;
+  cuts.chi2_max = (double)m.chi2_max;
+  const int64_t slots = ctx->max_hits / 3 + 2;
+  const int64_t lanes = std::min<int64_t>(std::min(tracks->track_capacity, slots), (int64_t)ctx->n_cu * 4 * 256);
+  HIP_TRY(launch_merge(inputs_of(in), in->n_sectors, ctx->n_rows, ctx->row_x, ctx->consts, cuts,
+                       trk->tracklet_offset, T, trk->tracklet_capacity, R, F, M, ctx->ws, slots,
+                       (int)((lanes + 255) / 256), st));
   return CATPC_OK;
 }
 

@@ -65,6 +65,8 @@ struct Workspace {
   int32_t* sel_cnt;              // [H/3 + 2] hits a selected tracklet keeps, or -1
   int2* sel_loc;                 // [H/3 + 2] track and hit offsets within the slot's group of 1024
   longlong2* sel_grp;            // [(H/3)/1024 + 8] group offsets
+  float4* mrec;                  // [H/3 + 2] segment merging: start x, y, z of each track's tracklet, rows
+  unsigned long long* mkey;      // [H/3 + 2] segment merging: best predecessor as (chi^2 bits, track)
   unsigned long long* counters; // [kNumCounters], see kCtr*
 };
 
@@ -113,6 +115,20 @@ struct FitsOut {
   int64_t capacity;
 };
 
+struct MergeOut {
+  int32_t* next;
+  int32_t* prev;
+  int32_t* head;
+  float* chi2;
+  int64_t capacity;
+};
+
+struct MergeCuts {
+  int32_t max_gap;
+  double window;
+  double chi2_max;
+};
+
 struct TrackletOut {
   float* x_ref;
   float* param;
@@ -156,6 +172,10 @@ hipError_t launch_select(const Inputs& in, int S, const int64_t* toff, int64_t c
 hipError_t launch_fullfit(const Inputs& in, int S, int n_rows, const float* row_x, const Consts& c,
                           const int64_t* toff, const TrackletOut& trk, int64_t trk_cap, const TracksOut& tr,
                           const FitsOut& out, const Workspace& ws, int grid, hipStream_t st);
+hipError_t launch_merge(const Inputs& in, int S, int n_rows, const float* row_x, const Consts& c,
+                        const MergeCuts& m, const int64_t* toff, const TrackletOut& trk, int64_t trk_cap,
+                        const TracksOut& tr, const FitsOut& fits, const MergeOut& out, const Workspace& ws,
+                        int64_t max_slots, int grid, hipStream_t st);
 hipError_t launch_refit64(const Inputs& in, Span sp, int n_rows, const float* row_x, const Consts& c,
                           const Workspace& ws, const int64_t* toff, int64_t first, int64_t cap,
                           const TrackletOut& out, int grid, hipStream_t st);

@@ -1456,6 +1456,177 @@ __global__ __launch_bounds__(256) void k_fullfit(Inputs in, int S, int R, const 
     atomicOr(&ws.counters[kCtrError], 32ull);
 }
 
+// ------------------------------------------------- segment merging
+// Per track, for the pair scan: the tracklet's start x, y, z and its first
+// row | (row of the track's outermost hit << 16), or -1 in .w when the track
+// takes no part (refit not done, or an inconsistent record).  Also resets
+// the outputs and the best-predecessor keys.
+__global__ __launch_bounds__(256) void k_merge_prep(Inputs in, int S, int R, const int64_t* toff, TrackletOut trk,
+                                                    int64_t trk_cap, TracksOut tr, FitsOut fits, MergeOut out,
+                                                    Workspace ws, int64_t n_max) {
+  const int64_t n = min(tr.track_offset[S], n_max);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+    const int s = sector_of(tr.track_offset, 0, S, t);
+    const int64_t a = in.hit_offset[s];
+    const int32_t ns = (int32_t)(in.hit_offset[s + 1] - a);
+    const int64_t slot = toff[s] + tr.track_tracklet[t];
+    const int nh = tr.track_n_hits[t];
+    const int64_t h0 = tr.track_hit_offset[t];
+    bool ok = fits.flags[t] == 1 && nh > 0 && slot >= 0 && slot < trk_cap && h0 >= 0 && h0 + nh <= tr.hit_capacity;
+    int32_t hl = 0, last = 0, first = 0;
+    if (ok) {
+      hl = tr.track_hits[h0 + nh - 1];
+      ok = hl >= 0 && hl < ns;
+    }
+    if (ok) {
+      last = in.row[a + hl];
+      first = trk.first_row[slot];
+      ok = last >= 0 && last < R && first >= 0 && first < R;
+    }
+    float4 rec = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+    if (ok) rec = make_float4(trk.x_ref[slot], trk.param[5 * slot], trk.param[5 * slot + 1], __int_as_float(first | (last << 16)));
+    ws.mrec[t] = rec;
+    ws.mkey[t] = ~0ull;
+    out.next[t] = -1;
+    out.prev[t] = -1;
+    out.head[t] = (int32_t)t;
+    out.chi2[t] = -1.f;
+  }
+}
+
+// chi^2 of segment A's end (x, p, packed C, at row a_last) against the start
+// state bp/bC of a continuation starting at row b_first, or -1 when the
+// transport stops or the summed covariance is not positive definite.
+__device__ __noinline__ double merge_chi2(double x, const double* pa, const float* __restrict__ Ca, int a_last,
+                                          int b_first, const float* __restrict__ bp, const float* __restrict__ bC,
+                                          const float* __restrict__ row_x, double kb) {
+  double p[5], C[15];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) p[i] = pa[i];
+#pragma unroll
+  for (int q = 0; q < 15; ++q) C[q] = (double)Ca[q];
+  for (int r = a_last + 1; r <= b_first; ++r) {
+    FitJac J;
+    if (ff_transport(x, p, (double)row_x[r], kb, &J)) return -1.0;
+    ff_transport_cov(C, J);
+  }
+  double d[5], L[5][5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) d[i] = (double)bp[i] - p[i];
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) L[i][j] = 0.0;
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      double acc = C[ff_tri(i, j)] + (double)bC[ff_tri(i, j)];
+#pragma unroll
+      for (int q = 0; q < j; ++q) acc = acc - L[i][q] * L[j][q];
+      if (i == j) {
+        if (!(acc > 0.0)) return -1.0;
+        L[i][i] = sqrt(acc);
+      } else {
+        L[i][j] = acc / L[j][j];
+      }
+    }
+  double w[5], chi2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    double acc = d[i];
+#pragma unroll
+    for (int q = 0; q < i; ++q) acc = acc - L[i][q] * w[q];
+    w[i] = acc / L[i][i];
+    chi2 = chi2 + w[i] * w[i];
+  }
+  return chi2;
+}
+
+// One lane per segment A: every segment B of the sector is a candidate; the
+// lane keeps A's best B (tentative next) and takes the atomic minimum of
+// (chi^2 bits, A) on B's key, which leaves B's best predecessor there.
+__global__ __launch_bounds__(256) void k_merge_pairs(int S, const float* __restrict__ row_x, Consts c, MergeCuts m,
+                                                     const int64_t* toff, TrackletOut trk, TracksOut tr,
+                                                     FitsOut fits, MergeOut out, Workspace ws, int64_t n_max) {
+  const int64_t n = min(tr.track_offset[S], n_max);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t A = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; A < n; A += stride) {
+    const int wa = __float_as_int(ws.mrec[A].w);
+    if (wa < 0) continue;
+    const int a_last = wa >> 16;
+    const int s = sector_of(tr.track_offset, 0, S, A);
+    const int64_t k0 = tr.track_offset[s], k1 = min(tr.track_offset[s + 1], n);
+    const double ax = (double)fits.x[A];
+    double ap[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) ap[i] = (double)fits.param[5 * A + i];
+    const double ca = sqrt(1.0 - ap[2] * ap[2]);
+    const double ty = ap[2] / ca, tz = ap[3] / ca;
+    int64_t best = -1;
+    float best_c = 0.f;
+    for (int64_t B = k0; B < k1; ++B) {
+      if (B == A) continue;
+      const float4 rb = ws.mrec[B];
+      const int wb = __float_as_int(rb.w);
+      if (wb < 0) continue;
+      const int b_first = wb & 0xffff;
+      if (!(b_first > a_last && b_first - a_last <= m.max_gap)) continue;
+      const double dx0 = (double)rb.x - ax;
+      const double yw = (ap[0] + dx0 * ty) - (double)rb.y;
+      const double zw = (ap[1] + dx0 * tz) - (double)rb.z;
+      if (!(fabs(yw) <= m.window && fabs(zw) <= m.window)) continue;
+      const int64_t sb = toff[s] + tr.track_tracklet[B];
+      const double chi2 = merge_chi2(ax, ap, fits.cov + 15 * A, a_last, b_first, trk.param + 5 * sb,
+                                     trk.cov + 15 * sb, row_x, c.kbd);
+      if (!(chi2 >= 0.0 && chi2 <= m.chi2_max)) continue;
+      const float cf = (float)chi2;
+      if (best < 0 || cf < best_c) {
+        best = B;
+        best_c = cf;
+      }
+      atomicMin(&ws.mkey[B], ((unsigned long long)__float_as_uint(cf) << 32) | (unsigned long long)(uint32_t)A);
+    }
+    if (best >= 0) {
+      out.next[A] = (int32_t)best;
+      out.chi2[A] = best_c;
+    }
+  }
+}
+
+// Keep A's link only when A is its continuation's best predecessor.
+__global__ __launch_bounds__(256) void k_merge_link(int S, TracksOut tr, MergeOut out, Workspace ws, int64_t n_max) {
+  const int64_t n = min(tr.track_offset[S], n_max);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t A = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; A < n; A += stride) {
+    const int32_t B = out.next[A];
+    if (B < 0) continue;
+    if ((uint32_t)(ws.mkey[B] & 0xffffffffull) == (uint32_t)A) {
+      out.prev[B] = (int32_t)A;
+    } else {
+      out.next[A] = -1;
+      out.chi2[A] = -1.f;
+    }
+  }
+}
+
+// First segment of each chain (rows rise strictly along a chain, so a walk
+// is at most R steps).
+__global__ __launch_bounds__(256) void k_merge_head(int S, int R, TracksOut tr, MergeOut out, int64_t n_max) {
+  const int64_t n = min(tr.track_offset[S], n_max);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+    int32_t h = (int32_t)t;
+    for (int i = 0; i < R; ++i) {
+      const int32_t p = out.prev[h];
+      if (p < 0) break;
+      h = p;
+    }
+    out.head[t] = h;
+  }
+}
+
 // ------------------------------------------------- binary64-covariance refit
 struct MTrk {
   float x, y, z, s, l, q;
@@ -1759,6 +1930,20 @@ hipError_t launch_fullfit(const Inputs& in, int S, int n_rows, const float* row_
                           const FitsOut& out, const Workspace& ws, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_fullfit, dim3(grid), dim3(256), 0, st, in, S, n_rows, row_x, c, toff, trk, trk_cap, tr, out,
                      ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge(const Inputs& in, int S, int n_rows, const float* row_x, const Consts& c,
+                        const MergeCuts& m, const int64_t* toff, const TrackletOut& trk, int64_t trk_cap,
+                        const TracksOut& tr, const FitsOut& fits, const MergeOut& out, const Workspace& ws,
+                        int64_t max_slots, int grid, hipStream_t st) {
+  const int64_t n_max = std::min(std::min(tr.track_capacity, fits.capacity), std::min(out.capacity, max_slots));
+  hipLaunchKernelGGL(k_merge_prep, dim3(grid), dim3(256), 0, st, in, S, n_rows, toff, trk, trk_cap, tr, fits, out,
+                     ws, n_max);
+  hipLaunchKernelGGL(k_merge_pairs, dim3(grid), dim3(256), 0, st, S, row_x, c, m, toff, trk, tr, fits, out, ws,
+                     n_max);
+  hipLaunchKernelGGL(k_merge_link, dim3(grid), dim3(256), 0, st, S, tr, out, ws, n_max);
+  hipLaunchKernelGGL(k_merge_head, dim3(grid), dim3(256), 0, st, S, n_rows, tr, out, n_max);
   return hipGetLastError();
 }
 

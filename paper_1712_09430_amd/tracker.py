@@ -147,6 +147,26 @@ class DeviceFits:
                 "ndf": g(self.ndf), "flags": g(self.flags)}
 
 
+class DeviceMerges:
+    """Output buffers of the segment merging: one entry per track slot."""
+
+    def __init__(self, capacity, device="cuda:0"):
+        dev = _need_gpu(device)
+        e = lambda dt: torch.empty(capacity, dtype=dt, device=dev)
+        self.capacity = int(capacity)
+        self.next, self.prev, self.head = e(torch.int32), e(torch.int32), e(torch.int32)
+        self.chi2 = e(torch.float32)
+        s = C.catpc_merges()
+        for f in ("next", "prev", "head", "chi2"):
+            setattr(s, f, _ptr(getattr(self, f)))
+        s.capacity = self.capacity
+        self.struct = s
+
+    def numpy(self, n):
+        g = lambda t: t[:n].cpu().numpy()
+        return {"next": g(self.next), "prev": g(self.prev), "head": g(self.head), "chi2": g(self.chi2)}
+
+
 class Tracker:
     """One catpc context on one device."""
 
@@ -227,6 +247,17 @@ class Tracker:
         """Enqueue the full Kalman refit of the selected tracks."""
         with torch.cuda.device(self.device):
             C.catpc_refit_tracks(self.ctx, hits.struct, out.struct, tracks.struct, fits.struct, _stream(self.device))
+
+    def merges_output(self, tracks):
+        """Merge buffers for every track slot of `tracks`."""
+        return DeviceMerges(max(int(tracks.struct.track_capacity), 1), self.device)
+
+    def merge(self, hits, out, tracks, fits, merges, cuts=None):
+        """Enqueue the merging of track segments inside each sector; `cuts`
+        (catpc_merge_params) None takes the defaults."""
+        with torch.cuda.device(self.device):
+            C.catpc_merge_tracks(self.ctx, hits.struct, out.struct, tracks.struct, fits.struct, cuts,
+                                 merges.struct, _stream(self.device))
 
     def select_result(self):
         """Synchronise; (n_tracks, n_track_hits)."""

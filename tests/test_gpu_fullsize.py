@@ -90,3 +90,43 @@ def test_batch64_sampled_sectors_bit_exact_and_global_properties():
     nsz = sizes[sec_of_slot][:, None]
     assert np.all((rh == -1) | ((rh >= 0) & (rh < nsz)))
     assert np.array_equal((rh >= 0).sum(1), trk["n_hits"])
+
+
+def test_batch64_merge_sampled_sectors_bit_exact():
+    """Selection, refit and segment merging after the bench configuration's
+    track call on the 64-event batch: sampled sectors against the oracle."""
+    from _harness import chains, oracle_merge_sector, oracle_params
+    b = synth.batch_workload(seed=1, n_events=64)
+    tr, hits, out, n, p = run_bench_config(b)
+    tracks = tr.tracks_output(hits, out)
+    tr.select(hits, out, tracks)
+    nt, nh = tr.select_result()
+    fits = tr.fits_output(tracks)
+    tr.refit(hits, out, tracks, fits)
+    merges = tr.merges_output(tracks)
+    tr.merge(hits, out, tracks, fits, merges)
+    torch.cuda.synchronize()
+    g, m = tracks.numpy(nt, nh), merges.numpy(nt)
+    sizes = np.diff(b.hit_offset)
+    rng = np.random.default_rng(77)
+    sample = sorted(set(np.argsort(sizes)[-2:].tolist()) | set(rng.choice(b.n_sectors, 8, replace=False).tolist()))
+    P = oracle_params(p)
+
+    def one(s):
+        nxt, chi2, _ = oracle_merge_sector(b, s, P)
+        k0, k1 = int(g["track_offset"][s]), int(g["track_offset"][s + 1])
+        if k1 - k0 != len(nxt):
+            return [f"sector {s}: track count"]
+        prev, head = chains(nxt)
+        bad = []
+        if not np.array_equal(m["next"][k0:k1], np.where(nxt >= 0, nxt + k0, -1)):
+            bad.append(f"sector {s}: next")
+        if not np.array_equal(m["head"][k0:k1], head + k0):
+            bad.append(f"sector {s}: head")
+        if not np.array_equal(m["chi2"][k0:k1].view(np.uint32), chi2.view(np.uint32)):
+            bad.append(f"sector {s}: chi2")
+        return bad
+
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        bad = [x for r in ex.map(one, sample) for x in r]
+    assert not bad, "\n".join(bad)
