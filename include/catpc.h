@@ -82,6 +82,9 @@ typedef struct {
                             0 (the compiler's own allocation), 5, 6 or 8 (may spill to scratch) [0] */
   int32_t tc_sync;       /* 1: the lanes of a wave step through the pad rows together, reading the same row
                             grids at the same time [0] */
+  int32_t merge_pair_cap; /* segment merging: at most this many candidate pairs are listed for the per-pair
+                             pass, 0 for the whole list (4 per track slot); a track with a pair beyond the
+                             list evaluates all its pairs in its own lane [0] */
 } catpc_tuning;
 
 /* Input hits (device pointers). */

@@ -45,7 +45,8 @@ class catpc_tuning(ctypes.Structure):
     _fields_ = [("bin_hits", ctypes.c_float), ("nf_block", ctypes.c_int32), ("tc_block", ctypes.c_int32),
                 ("tc_waves_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("nf_rows", ctypes.c_int32), ("nf_lds_kb", ctypes.c_int32), ("tc_xcd", ctypes.c_int32),
-                ("tc_occupancy", ctypes.c_int32), ("tc_sync", ctypes.c_int32)]
+                ("tc_occupancy", ctypes.c_int32), ("tc_sync", ctypes.c_int32),
+                ("merge_pair_cap", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p

@@ -38,7 +38,7 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
   size_t row_first, hdr, bins, sorted, raw_up, raw_dn, mask, blk_cnt, blk_off, grp_off, start_glob, chain,
-      owner, sel_cnt, sel_loc, sel_grp, mrec, mkey, counters;
+      owner, sel_cnt, sel_loc, sel_grp, mrec, mkey_a, mkey_b, mpair, mover, counters;
   size_t total;
 };
 
@@ -65,7 +65,10 @@ Layout plan(int32_t R, int64_t H, int32_t S) {
   L.sel_loc = take(sizeof(int2) * slots);
   L.sel_grp = take(sizeof(longlong2) * (slots / 1024 + 8));
   L.mrec = take(sizeof(float4) * slots);
-  L.mkey = take(sizeof(unsigned long long) * slots);
+  L.mkey_a = take(sizeof(unsigned long long) * slots);
+  L.mkey_b = take(sizeof(unsigned long long) * slots);
+  L.mpair = take(sizeof(int2) * (size_t)kMergePairsPerSlot * slots);
+  L.mover = take(sizeof(int32_t) * slots);
   L.counters = take(sizeof(unsigned long long) * kNumCounters);
   L.total = o;
   return L;
@@ -370,6 +373,7 @@ void catpc_default_tuning(catpc_tuning* t) {
   t->tc_xcd = 1;
   t->tc_occupancy = 0;
   t->tc_sync = 0;
+  t->merge_pair_cap = 0;
 }
 
 int32_t catpc_row_stride(int32_t n_rows) { return n_rows > 0 ? row_stride(n_rows) : 0; }
@@ -451,7 +455,10 @@ catpc_status catpc_create(int32_t n_rows, const float* row_x, const catpc_params
       w.sel_loc = (int2*)(b + L.sel_loc);
       w.sel_grp = (longlong2*)(b + L.sel_grp);
       w.mrec = (float4*)(b + L.mrec);
-      w.mkey = (unsigned long long*)(b + L.mkey);
+      w.mkey_a = (unsigned long long*)(b + L.mkey_a);
+      w.mkey_b = (unsigned long long*)(b + L.mkey_b);
+      w.mpair = (int2*)(b + L.mpair);
+      w.mover = (int32_t*)(b + L.mover);
       w.counters = (unsigned long long*)(b + L.counters);
       e = hipMemset(w.counters, 0, sizeof(unsigned long long) * kNumCounters);
     }
@@ -500,6 +507,7 @@ catpc_status catpc_set_tuning(catpc_ctx* ctx, const catpc_tuning* t) {
   if (t->tc_occupancy != 0 && t->tc_occupancy != 5 && t->tc_occupancy != 6 && t->tc_occupancy != 8)
     return fail(CATPC_E_INVALID, "tc_occupancy must be 0, 5, 6 or 8");
   if (t->tc_sync < 0 || t->tc_sync > 1) return fail(CATPC_E_INVALID, "tc_sync must be 0 or 1");
+  if (t->merge_pair_cap < 0) return fail(CATPC_E_INVALID, "merge_pair_cap must be >= 0");
   ctx->tuning = *t;
   return CATPC_OK;
 }
@@ -829,7 +837,7 @@ catpc_status catpc_merge_tracks(catpc_ctx* ctx, const catpc_input* in, const cat
   const int64_t lanes = std::min<int64_t>(std::min(tracks->track_capacity, slots), (int64_t)ctx->n_cu * 4 * 256);
   HIP_TRY(launch_merge(inputs_of(in), in->n_sectors, ctx->n_rows, ctx->row_x, ctx->consts, cuts,
                        trk->tracklet_offset, T, trk->tracklet_capacity, R, F, M, ctx->ws, slots,
-                       (int)((lanes + 255) / 256), st));
+                       (int)((lanes + 255) / 256), ctx->n_cu * 8, ctx->tuning.merge_pair_cap > 0 ? (int64_t)ctx->tuning.merge_pair_cap : kMergePairsPerSlot * slots, st));
   return CATPC_OK;
 }
 

@@ -66,7 +66,10 @@ struct Workspace {
   int2* sel_loc;                 // [H/3 + 2] track and hit offsets within the slot's group of 1024
   longlong2* sel_grp;            // [(H/3)/1024 + 8] group offsets
   float4* mrec;                  // [H/3 + 2] segment merging: start x, y, z of each track's tracklet, rows
-  unsigned long long* mkey;      // [H/3 + 2] segment merging: best predecessor as (chi^2 bits, track)
+  unsigned long long* mkey_a;    // [H/3 + 2] segment merging: best continuation as (chi^2 bits, track)
+  unsigned long long* mkey_b;    // [H/3 + 2] segment merging: best predecessor as (chi^2 bits, track)
+  int2* mpair;                   // [kMergePairsPerSlot * (H/3 + 2)] segment merging: candidate pairs
+  int32_t* mover;                // [H/3 + 2] segment merging: 1 when a pair of the track did not fit the list
   unsigned long long* counters; // [kNumCounters], see kCtr*
 };
 
@@ -79,7 +82,9 @@ constexpr int kCtrError = 8;     // bit 0: invalid rows seen; bit 1: selection s
 constexpr int kCtrCounts = 9;    // [9, 13): transports, updates, gated candidates, row searches
 constexpr int kCtrSelTracks = 13;  // selected tracks
 constexpr int kCtrSelHits = 14;    // hits they keep
+constexpr int kCtrMergePairs = 15;  // candidate pairs of the segment merging
 constexpr int kNumCounters = 16;
+constexpr int64_t kMergePairsPerSlot = 4;  // candidate-pair list length per track slot
 
 // Call geometry: sectors [s0, s1), hits [h0, h1) (global indices).
 struct Span {
@@ -175,7 +180,7 @@ hipError_t launch_fullfit(const Inputs& in, int S, int n_rows, const float* row_
 hipError_t launch_merge(const Inputs& in, int S, int n_rows, const float* row_x, const Consts& c,
                         const MergeCuts& m, const int64_t* toff, const TrackletOut& trk, int64_t trk_cap,
                         const TracksOut& tr, const FitsOut& fits, const MergeOut& out, const Workspace& ws,
-                        int64_t max_slots, int grid, hipStream_t st);
+                        int64_t max_slots, int grid, int pair_grid, int64_t pair_cap, hipStream_t st);
 hipError_t launch_refit64(const Inputs& in, Span sp, int n_rows, const float* row_x, const Consts& c,
                           const Workspace& ws, const int64_t* toff, int64_t first, int64_t cap,
                           const TrackletOut& out, int grid, hipStream_t st);

@@ -1457,13 +1457,14 @@ __global__ __launch_bounds__(256) void k_fullfit(Inputs in, int S, int R, const 
 }
 
 // ------------------------------------------------- segment merging
-// Per track, for the pair scan: the tracklet's start x, y, z and its first
-// row | (row of the track's outermost hit << 16), or -1 in .w when the track
-// takes no part (refit not done, or an inconsistent record).  Also resets
-// the outputs and the best-predecessor keys.
+// Per track, for the candidate scan: the tracklet's start x, y, z and its
+// first row | (row of the track's outermost hit << 16), or -1 in .w when the
+// track takes no part (refit not done, or an inconsistent record).  Also
+// resets the outputs, both best-partner keys and the pair counter.
 __global__ __launch_bounds__(256) void k_merge_prep(Inputs in, int S, int R, const int64_t* toff, TrackletOut trk,
                                                     int64_t trk_cap, TracksOut tr, FitsOut fits, MergeOut out,
                                                     Workspace ws, int64_t n_max) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) ws.counters[kCtrMergePairs] = 0ull;
   const int64_t n = min(tr.track_offset[S], n_max);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
@@ -1487,7 +1488,9 @@ __global__ __launch_bounds__(256) void k_merge_prep(Inputs in, int S, int R, con
     float4 rec = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
     if (ok) rec = make_float4(trk.x_ref[slot], trk.param[5 * slot], trk.param[5 * slot + 1], __int_as_float(first | (last << 16)));
     ws.mrec[t] = rec;
-    ws.mkey[t] = ~0ull;
+    ws.mkey_a[t] = ~0ull;
+    ws.mkey_b[t] = ~0ull;
+    ws.mover[t] = 0;
     out.next[t] = -1;
     out.prev[t] = -1;
     out.head[t] = (int32_t)t;
@@ -1495,17 +1498,22 @@ __global__ __launch_bounds__(256) void k_merge_prep(Inputs in, int S, int R, con
   }
 }
 
-// chi^2 of segment A's end (x, p, packed C, at row a_last) against the start
-// state bp/bC of a continuation starting at row b_first, or -1 when the
-// transport stops or the summed covariance is not positive definite.
-__device__ __noinline__ double merge_chi2(double x, const double* pa, const float* __restrict__ Ca, int a_last,
-                                          int b_first, const float* __restrict__ bp, const float* __restrict__ bC,
-                                          const float* __restrict__ row_x, double kb) {
-  double p[5], C[15];
+// chi^2 of segment A's end state against the start state of a continuation B
+// (A carried row by row with the refit's transport and Jacobian), or -1 when
+// the transport stops or the summed covariance is not positive definite.
+__device__ __forceinline__ double merge_chi2(int64_t A, int64_t B, int s, const float* __restrict__ row_x, double kb,
+                                             const int64_t* toff, const TrackletOut& trk, const TracksOut& tr,
+                                             const FitsOut& fits, const Workspace& ws) {
+  const int a_last = __float_as_int(ws.mrec[A].w) >> 16;
+  const int b_first = __float_as_int(ws.mrec[B].w) & 0xffff;
+  const int64_t sb = toff[s] + tr.track_tracklet[B];
+  const float* __restrict__ bp = trk.param + 5 * sb;
+  const float* __restrict__ bC = trk.cov + 15 * sb;
+  double x = (double)fits.x[A], p[5], C[15];
 #pragma unroll
-  for (int i = 0; i < 5; ++i) p[i] = pa[i];
+  for (int i = 0; i < 5; ++i) p[i] = (double)fits.param[5 * A + i];
 #pragma unroll
-  for (int q = 0; q < 15; ++q) C[q] = (double)Ca[q];
+  for (int q = 0; q < 15; ++q) C[q] = (double)fits.cov[15 * A + q];
   for (int r = a_last + 1; r <= b_first; ++r) {
     FitJac J;
     if (ff_transport(x, p, (double)row_x[r], kb, &J)) return -1.0;
@@ -1544,70 +1552,179 @@ __device__ __noinline__ double merge_chi2(double x, const double* pa, const floa
   return chi2;
 }
 
-// One lane per segment A: every segment B of the sector is a candidate; the
-// lane keeps A's best B (tentative next) and takes the atomic minimum of
-// (chi^2 bits, A) on B's key, which leaves B's best predecessor there.
-__global__ __launch_bounds__(256) void k_merge_pairs(int S, const float* __restrict__ row_x, Consts c, MergeCuts m,
-                                                     const int64_t* toff, TrackletOut trk, TracksOut tr,
-                                                     FitsOut fits, MergeOut out, Workspace ws, int64_t n_max) {
-  const int64_t n = min(tr.track_offset[S], n_max);
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t A = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; A < n; A += stride) {
-    const int wa = __float_as_int(ws.mrec[A].w);
-    if (wa < 0) continue;
-    const int a_last = wa >> 16;
-    const int s = sector_of(tr.track_offset, 0, S, A);
-    const int64_t k0 = tr.track_offset[s], k1 = min(tr.track_offset[s + 1], n);
-    const double ax = (double)fits.x[A];
-    double ap[5];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) ap[i] = (double)fits.param[5 * A + i];
-    const double ca = sqrt(1.0 - ap[2] * ap[2]);
-    const double ty = ap[2] / ca, tz = ap[3] / ca;
-    int64_t best = -1;
-    float best_c = 0.f;
-    for (int64_t B = k0; B < k1; ++B) {
-      if (B == A) continue;
-      const float4 rb = ws.mrec[B];
-      const int wb = __float_as_int(rb.w);
-      if (wb < 0) continue;
-      const int b_first = wb & 0xffff;
-      if (!(b_first > a_last && b_first - a_last <= m.max_gap)) continue;
-      const double dx0 = (double)rb.x - ax;
-      const double yw = (ap[0] + dx0 * ty) - (double)rb.y;
-      const double zw = (ap[1] + dx0 * tz) - (double)rb.z;
-      if (!(fabs(yw) <= m.window && fabs(zw) <= m.window)) continue;
-      const int64_t sb = toff[s] + tr.track_tracklet[B];
-      const double chi2 = merge_chi2(ax, ap, fits.cov + 15 * A, a_last, b_first, trk.param + 5 * sb,
-                                     trk.cov + 15 * sb, row_x, c.kbd);
-      if (!(chi2 >= 0.0 && chi2 <= m.chi2_max)) continue;
-      const float cf = (float)chi2;
-      if (best < 0 || cf < best_c) {
-        best = B;
-        best_c = cf;
-      }
-      atomicMin(&ws.mkey[B], ((unsigned long long)__float_as_uint(cf) << 32) | (unsigned long long)(uint32_t)A);
-    }
-    if (best >= 0) {
-      out.next[A] = (int32_t)best;
-      out.chi2[A] = best_c;
-    }
+// A compatible pair takes the atomic minimum of (chi^2 bits, partner) on both
+// keys: A's key ends at its best continuation, B's at its best predecessor,
+// whatever the order of the atomics (chi^2 >= 0, so its bits order as the
+// values; equal values order by the index).
+__device__ __forceinline__ void merge_pair(int64_t A, int64_t B, int s, const float* __restrict__ row_x,
+                                           const Consts& c, const MergeCuts& m, const int64_t* toff,
+                                           const TrackletOut& trk, const TracksOut& tr, const FitsOut& fits,
+                                           const Workspace& ws) {
+  const double chi2 = merge_chi2(A, B, s, row_x, c.kbd, toff, trk, tr, fits, ws);
+  if (!(chi2 >= 0.0 && chi2 <= m.chi2_max)) return;
+  const unsigned long long hi = (unsigned long long)__float_as_uint((float)chi2) << 32;
+  atomicMin(&ws.mkey_a[A], hi | (unsigned long long)(uint32_t)B);
+  atomicMin(&ws.mkey_b[B], hi | (unsigned long long)(uint32_t)A);
+}
+
+// The cheap tests of a pair (rows, straight-line window) for segment A
+// against every segment B of its sector; f(B) for each pair that passes.
+template <class F>
+__device__ __forceinline__ void merge_scan(int64_t A, int64_t n, int S, const MergeCuts& m, const TracksOut& tr,
+                                           const FitsOut& fits, const Workspace& ws, F&& f) {
+  const int wa = __float_as_int(ws.mrec[A].w);
+  if (wa < 0) return;
+  const int a_last = wa >> 16;
+  const int s = sector_of(tr.track_offset, 0, S, A);
+  const int64_t k0 = tr.track_offset[s], k1 = min(tr.track_offset[s + 1], n);
+  const double ax = (double)fits.x[A];
+  const double ay = (double)fits.param[5 * A], az = (double)fits.param[5 * A + 1];
+  const double as = (double)fits.param[5 * A + 2], al = (double)fits.param[5 * A + 3];
+  const double ca = sqrt(1.0 - as * as);
+  const double ty = as / ca, tz = al / ca;
+  for (int64_t B = k0; B < k1; ++B) {
+    const float4 rb = ws.mrec[B];
+    const int wb = __float_as_int(rb.w);
+    if (B == A || wb < 0) continue;
+    const int b_first = wb & 0xffff;
+    if (!(b_first > a_last && b_first - a_last <= m.max_gap)) continue;
+    const double dx0 = (double)rb.x - ax;
+    const double yw = (ay + dx0 * ty) - (double)rb.y;
+    const double zw = (az + dx0 * tz) - (double)rb.z;
+    if (!(fabs(yw) <= m.window && fabs(zw) <= m.window)) continue;
+    f(B, s);
   }
 }
 
-// Keep A's link only when A is its continuation's best predecessor.
+// One workgroup per sector (grid-stride over sectors), one lane per segment
+// A; the sector's segment records are staged in LDS in tiles and every lane
+// walks the same tile entry at the same time (a broadcast read), so the walk
+// is uniform across the wave.  The pairs that pass the cheap tests go to the
+// list through chunks of 64 entries that a wave reserves with one atomic (a
+// counter hit once per pair serialises in L2); a wave's last chunk is padded
+// with (-1, -1).  A segment with a pair beyond the list is marked for
+// k_merge_over.
+constexpr int kMergeTile = 2048;  // segment records per LDS tile (32 KiB)
+constexpr int kMergeChunk = 64;   // list entries a wave reserves at a time
+
+__global__ __launch_bounds__(256) void k_merge_cand(int S, MergeCuts m, TracksOut tr, FitsOut fits, Workspace ws,
+                                                    int64_t n_max, int64_t pair_cap) {
+  __shared__ float4 recs[kMergeTile];
+  const int64_t n = min(tr.track_offset[S], n_max);
+  const int lane = threadIdx.x & 63;
+  int64_t cbase = 0;      // the wave's current chunk
+  int used = kMergeChunk;  // entries of it taken (full: no chunk yet)
+  for (int s = blockIdx.x; s < S; s += gridDim.x) {
+    const int64_t k0 = min(tr.track_offset[s], n), k1 = min(tr.track_offset[s + 1], n);
+    for (int64_t a0 = k0; a0 < k1; a0 += blockDim.x) {
+      const int64_t A = a0 + threadIdx.x;
+      int a_last = -1;
+      double ax = 0.0, ay = 0.0, az = 0.0, ty = 0.0, tz = 0.0;
+      if (A < k1) {
+        const int wa = __float_as_int(ws.mrec[A].w);
+        if (wa >= 0) {
+          a_last = wa >> 16;
+          ax = (double)fits.x[A];
+          ay = (double)fits.param[5 * A];
+          az = (double)fits.param[5 * A + 1];
+          const double as = (double)fits.param[5 * A + 2], al = (double)fits.param[5 * A + 3];
+          const double ca = sqrt(1.0 - as * as);
+          ty = as / ca;
+          tz = al / ca;
+        }
+      }
+      for (int64_t b0 = k0; b0 < k1; b0 += kMergeTile) {
+        const int nb = (int)min<int64_t>(kMergeTile, k1 - b0);
+        __syncthreads();
+        for (int i = threadIdx.x; i < nb; i += blockDim.x) recs[i] = ws.mrec[b0 + i];
+        __syncthreads();
+        for (int i = 0; i < nb; ++i) {
+          const float4 rb = recs[i];
+          const int wb = __float_as_int(rb.w);
+          bool pass = false;
+          if (a_last >= 0 && wb >= 0 && b0 + i != A) {
+            const int b_first = wb & 0xffff;
+            if (b_first > a_last && b_first - a_last <= m.max_gap) {
+              const double dx0 = (double)rb.x - ax;
+              const double yw = (ay + dx0 * ty) - (double)rb.y;
+              const double zw = (az + dx0 * tz) - (double)rb.z;
+              pass = fabs(yw) <= m.window && fabs(zw) <= m.window;
+            }
+          }
+          const unsigned long long bal = __ballot(pass);
+          if (bal == 0ull) continue;
+          const int cnt = __popcll(bal);
+          const bool grab = used + cnt > kMergeChunk;
+          int64_t nbase = cbase;
+          if (grab) {
+            unsigned long long g = 0ull;
+            if (lane == 0) g = atomicAdd(&ws.counters[kCtrMergePairs], (unsigned long long)kMergeChunk);
+            const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)g, 0);
+            const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(g >> 32), 0);
+            nbase = (int64_t)(((unsigned long long)hi << 32) | lo);
+          }
+          if (pass) {
+            const int pos = used + __popcll(bal & ((1ull << lane) - 1ull));
+            const int64_t k = pos < kMergeChunk ? cbase + pos : nbase + (pos - kMergeChunk);
+            if (k < pair_cap)
+              ws.mpair[k] = make_int2((int32_t)A, (int32_t)(b0 + i));
+            else
+              ws.mover[A] = 1;
+          }
+          if (grab) {
+            cbase = nbase;
+            used = used + cnt - kMergeChunk;
+          } else {
+            used += cnt;
+          }
+        }
+      }
+    }
+  }
+  if (used < kMergeChunk && lane >= used && cbase + lane < pair_cap) ws.mpair[cbase + lane] = make_int2(-1, -1);
+}
+
+// Segments marked by k_merge_cand evaluate all their pairs themselves (a
+// pair that is also listed gives the same atomic minimum twice).
+__global__ __launch_bounds__(256) void k_merge_over(int S, const float* __restrict__ row_x, Consts c, MergeCuts m,
+                                                    const int64_t* toff, TrackletOut trk, TracksOut tr, FitsOut fits,
+                                                    Workspace ws, int64_t n_max) {
+  const int64_t n = min(tr.track_offset[S], n_max);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t A = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; A < n; A += stride) {
+    if (!ws.mover[A]) continue;
+    merge_scan(A, n, S, m, tr, fits, ws, [&](int64_t B, int s) {
+      merge_pair(A, B, s, row_x, c, m, toff, trk, tr, fits, ws);
+    });
+  }
+}
+
+// One lane per listed pair.
+__global__ __launch_bounds__(256) void k_merge_chi2(int S, const float* __restrict__ row_x, Consts c, MergeCuts m,
+                                                    const int64_t* toff, TrackletOut trk, TracksOut tr, FitsOut fits,
+                                                    Workspace ws, int64_t pair_cap) {
+  const int64_t np = min((int64_t)ws.counters[kCtrMergePairs], pair_cap);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < np; k += stride) {
+    const int2 ab = ws.mpair[k];
+    if (ab.x < 0) continue;  // padding of a wave's last chunk
+    const int s = sector_of(tr.track_offset, 0, S, ab.x);
+    merge_pair(ab.x, ab.y, s, row_x, c, m, toff, trk, tr, fits, ws);
+  }
+}
+
+// Link A to its best continuation B when A is B's best predecessor.
 __global__ __launch_bounds__(256) void k_merge_link(int S, TracksOut tr, MergeOut out, Workspace ws, int64_t n_max) {
   const int64_t n = min(tr.track_offset[S], n_max);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t A = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; A < n; A += stride) {
-    const int32_t B = out.next[A];
-    if (B < 0) continue;
-    if ((uint32_t)(ws.mkey[B] & 0xffffffffull) == (uint32_t)A) {
-      out.prev[B] = (int32_t)A;
-    } else {
-      out.next[A] = -1;
-      out.chi2[A] = -1.f;
-    }
+    const unsigned long long ka = ws.mkey_a[A];
+    if (ka == ~0ull) continue;
+    const int32_t B = (int32_t)(ka & 0xffffffffull);
+    if ((uint32_t)(ws.mkey_b[B] & 0xffffffffull) != (uint32_t)A) continue;
+    out.next[A] = B;
+    out.chi2[A] = __uint_as_float((uint32_t)(ka >> 32));
+    out.prev[B] = (int32_t)A;
   }
 }
 
@@ -1936,12 +2053,16 @@ hipError_t launch_fullfit(const Inputs& in, int S, int n_rows, const float* row_
 hipError_t launch_merge(const Inputs& in, int S, int n_rows, const float* row_x, const Consts& c,
                         const MergeCuts& m, const int64_t* toff, const TrackletOut& trk, int64_t trk_cap,
                         const TracksOut& tr, const FitsOut& fits, const MergeOut& out, const Workspace& ws,
-                        int64_t max_slots, int grid, hipStream_t st) {
+                        int64_t max_slots, int grid, int pair_grid, int64_t pair_cap, hipStream_t st) {
   const int64_t n_max = std::min(std::min(tr.track_capacity, fits.capacity), std::min(out.capacity, max_slots));
+  pair_cap = std::max<int64_t>(0, std::min(pair_cap, kMergePairsPerSlot * max_slots));
   hipLaunchKernelGGL(k_merge_prep, dim3(grid), dim3(256), 0, st, in, S, n_rows, toff, trk, trk_cap, tr, fits, out,
                      ws, n_max);
-  hipLaunchKernelGGL(k_merge_pairs, dim3(grid), dim3(256), 0, st, S, row_x, c, m, toff, trk, tr, fits, out, ws,
-                     n_max);
+  hipLaunchKernelGGL(k_merge_cand, dim3((unsigned)std::max(1, std::min(S, 8 * pair_grid))), dim3(256), 0, st, S, m, tr,
+                     fits, ws, n_max, pair_cap);
+  hipLaunchKernelGGL(k_merge_chi2, dim3(pair_grid), dim3(256), 0, st, S, row_x, c, m, toff, trk, tr, fits, ws,
+                     pair_cap);
+  hipLaunchKernelGGL(k_merge_over, dim3(grid), dim3(256), 0, st, S, row_x, c, m, toff, trk, tr, fits, ws, n_max);
   hipLaunchKernelGGL(k_merge_link, dim3(grid), dim3(256), 0, st, S, tr, out, ws, n_max);
   hipLaunchKernelGGL(k_merge_head, dim3(grid), dim3(256), 0, st, S, n_rows, tr, out, n_max);
   return hipGetLastError();

@@ -102,6 +102,17 @@ def test_cuts_match_oracle(cuts):
     check_chains(g, m, nt, cuts[2])
 
 
+@pytest.mark.parametrize("cap", [1, 37, 150])
+def test_pair_list_overflow_gives_the_same_links(cap):
+    """A short candidate-pair list (tuning merge_pair_cap): the tracks whose
+    pairs did not fit evaluate them in their own lane; links unchanged."""
+    from paper_1712_09430_amd import catpc as C
+    b = synth.sector_workload(seed=1, n_tracks=300, dead_rows=DEAD)
+    tr, hits, out, st, n = run_gpu(b, tuning={"merge_pair_cap": cap})
+    g, f, m, nt = gpu_merges(tr, hits, out)
+    assert check(b, g, m, C.catpc_default_params(), [0]) > 100
+
+
 def test_no_dead_band_and_empty_sectors():
     from paper_1712_09430_amd import catpc as C
     b = synth.event_workload(seed=2, n_tracks=300)
