@@ -38,7 +38,7 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
   size_t row_first, hdr, bins, sorted, raw_up, raw_dn, mask, blk_cnt, blk_off, grp_off, start_glob, chain,
-      owner, sel_cnt, sel_loc, sel_grp, mrec, mkey_a, mkey_b, mpair, mover, counters;
+      owner, sel_cnt, sel_loc, sel_grp, mrec, mkey_a, mkey_b, mpair, mover, mslot, mchunk, counters;
   size_t total;
 };
 
@@ -69,6 +69,8 @@ Layout plan(int32_t R, int64_t H, int32_t S) {
   L.mkey_b = take(sizeof(unsigned long long) * slots);
   L.mpair = take(sizeof(int2) * (size_t)kMergePairsPerSlot * slots);
   L.mover = take(sizeof(int32_t) * slots);
+  L.mslot = take(sizeof(int32_t) * slots);
+  L.mchunk = take(sizeof(int32_t) * ((size_t)S + 1));
   L.counters = take(sizeof(unsigned long long) * kNumCounters);
   L.total = o;
   return L;
@@ -459,6 +461,8 @@ catpc_status catpc_create(int32_t n_rows, const float* row_x, const catpc_params
       w.mkey_b = (unsigned long long*)(b + L.mkey_b);
       w.mpair = (int2*)(b + L.mpair);
       w.mover = (int32_t*)(b + L.mover);
+      w.mslot = (int32_t*)(b + L.mslot);
+      w.mchunk = (int32_t*)(b + L.mchunk);
       w.counters = (unsigned long long*)(b + L.counters);
       e = hipMemset(w.counters, 0, sizeof(unsigned long long) * kNumCounters);
     }

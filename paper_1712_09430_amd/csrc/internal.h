@@ -70,6 +70,8 @@ struct Workspace {
   unsigned long long* mkey_b;    // [H/3 + 2] segment merging: best predecessor as (chi^2 bits, track)
   int2* mpair;                   // [kMergePairsPerSlot * (H/3 + 2)] segment merging: candidate pairs
   int32_t* mover;                // [H/3 + 2] segment merging: 1 when a pair of the track did not fit the list
+  int32_t* mslot;                // [H/3 + 2] segment merging: tracklet slot of each track, or -1
+  int32_t* mchunk;               // [S + 1] segment merging: first chunk of 256 tracks of each sector
   unsigned long long* counters; // [kNumCounters], see kCtr*
 };
 

@@ -1488,6 +1488,7 @@ __global__ __launch_bounds__(256) void k_merge_prep(Inputs in, int S, int R, con
     float4 rec = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
     if (ok) rec = make_float4(trk.x_ref[slot], trk.param[5 * slot], trk.param[5 * slot + 1], __int_as_float(first | (last << 16)));
     ws.mrec[t] = rec;
+    ws.mslot[t] = ok ? (int32_t)slot : -1;
     ws.mkey_a[t] = ~0ull;
     ws.mkey_b[t] = ~0ull;
     ws.mover[t] = 0;
@@ -1501,12 +1502,11 @@ __global__ __launch_bounds__(256) void k_merge_prep(Inputs in, int S, int R, con
 // chi^2 of segment A's end state against the start state of a continuation B
 // (A carried row by row with the refit's transport and Jacobian), or -1 when
 // the transport stops or the summed covariance is not positive definite.
-__device__ __forceinline__ double merge_chi2(int64_t A, int64_t B, int s, const float* __restrict__ row_x, double kb,
-                                             const int64_t* toff, const TrackletOut& trk, const TracksOut& tr,
-                                             const FitsOut& fits, const Workspace& ws) {
+__device__ __forceinline__ double merge_chi2(int64_t A, int64_t B, const float* __restrict__ row_x, double kb,
+                                             const TrackletOut& trk, const FitsOut& fits, const Workspace& ws) {
   const int a_last = __float_as_int(ws.mrec[A].w) >> 16;
   const int b_first = __float_as_int(ws.mrec[B].w) & 0xffff;
-  const int64_t sb = toff[s] + tr.track_tracklet[B];
+  const int64_t sb = ws.mslot[B];
   const float* __restrict__ bp = trk.param + 5 * sb;
   const float* __restrict__ bC = trk.cov + 15 * sb;
   double x = (double)fits.x[A], p[5], C[15];
@@ -1556,11 +1556,10 @@ __device__ __forceinline__ double merge_chi2(int64_t A, int64_t B, int s, const 
 // keys: A's key ends at its best continuation, B's at its best predecessor,
 // whatever the order of the atomics (chi^2 >= 0, so its bits order as the
 // values; equal values order by the index).
-__device__ __forceinline__ void merge_pair(int64_t A, int64_t B, int s, const float* __restrict__ row_x,
-                                           const Consts& c, const MergeCuts& m, const int64_t* toff,
-                                           const TrackletOut& trk, const TracksOut& tr, const FitsOut& fits,
+__device__ __forceinline__ void merge_pair(int64_t A, int64_t B, const float* __restrict__ row_x, const Consts& c,
+                                           const MergeCuts& m, const TrackletOut& trk, const FitsOut& fits,
                                            const Workspace& ws) {
-  const double chi2 = merge_chi2(A, B, s, row_x, c.kbd, toff, trk, tr, fits, ws);
+  const double chi2 = merge_chi2(A, B, row_x, c.kbd, trk, fits, ws);
   if (!(chi2 >= 0.0 && chi2 <= m.chi2_max)) return;
   const unsigned long long hi = (unsigned long long)__float_as_uint((float)chi2) << 32;
   atomicMin(&ws.mkey_a[A], hi | (unsigned long long)(uint32_t)B);
@@ -1596,92 +1595,138 @@ __device__ __forceinline__ void merge_scan(int64_t A, int64_t n, int S, const Me
   }
 }
 
-// One workgroup per sector (grid-stride over sectors), one lane per segment
+// Chunks of 256 segments per sector and their exclusive prefix over the
+// sectors (one workgroup of 1024; sectors in tiles of 1024).
+__global__ __launch_bounds__(1024) void k_merge_chunks(int S, TracksOut tr, Workspace ws, int64_t n_max) {
+  __shared__ int part[1024];
+  const int64_t n = min(tr.track_offset[S], n_max);
+  int carry = 0;
+  for (int base = 0; base < S; base += 1024) {
+    const int s = base + threadIdx.x;
+    int v = 0;
+    if (s < S) {
+      const int64_t k0 = min(tr.track_offset[s], n), k1 = min(tr.track_offset[s + 1], n);
+      v = (int)((k1 - k0 + 255) / 256);
+    }
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+      const int add = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+      __syncthreads();
+      part[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (s < S) ws.mchunk[s] = carry + part[threadIdx.x] - v;
+    carry += part[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ws.mchunk[S] = carry;
+}
+
+// One workgroup per chunk of 256 segments of a sector, one lane per segment
 // A; the sector's segment records are staged in LDS in tiles and every lane
 // walks the same tile entry at the same time (a broadcast read), so the walk
-// is uniform across the wave.  The pairs that pass the cheap tests go to the
-// list through chunks of 64 entries that a wave reserves with one atomic (a
-// counter hit once per pair serialises in L2); a wave's last chunk is padded
-// with (-1, -1).  A segment with a pair beyond the list is marked for
-// k_merge_over.
+// is uniform across the wave.  A lane queues up to kMergeQueue partners B
+// that pass the cheap tests in registers; when a queue is full, and at the
+// end of the chunk, the wave writes all queues to the list at positions
+// reserved with one atomic (a counter hit once per pair serialises in L2).
+// A segment with a pair beyond the list is marked for k_merge_over.
 constexpr int kMergeTile = 2048;  // segment records per LDS tile (32 KiB)
-constexpr int kMergeChunk = 64;   // list entries a wave reserves at a time
+constexpr int kMergeQueue = 4;    // partners a lane holds before the wave writes them out
+
+__device__ __forceinline__ void merge_flush(int64_t A, int qn, int32_t q0, int32_t q1, int32_t q2, int32_t q3,
+                                            int lane, int64_t pair_cap, Workspace& ws) {
+  // qn in [0, 4]: the wave's total and this lane's offset from the bits of qn
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const unsigned long long b0 = __ballot(qn & 1), b1 = __ballot(qn & 2), b2 = __ballot(qn & 4);
+  const int total = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
+  if (total == 0) return;
+  const int off = __popcll(b0 & below) + 2 * __popcll(b1 & below) + 4 * __popcll(b2 & below);
+  unsigned long long g = 0ull;
+  if (lane == 0) g = atomicAdd(&ws.counters[kCtrMergePairs], (unsigned long long)total);
+  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)g, 0);
+  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(g >> 32), 0);
+  const int64_t base = (int64_t)(((unsigned long long)hi << 32) | lo) + off;
+  // the lane's queued partners are q0 .. q[qn - 1]
+  const int32_t q[kMergeQueue] = {q0, q1, q2, q3};
+#pragma unroll
+  for (int j = 0; j < kMergeQueue; ++j) {
+    if (j < qn) {
+      const int64_t k = base + j;
+      if (k < pair_cap)
+        ws.mpair[k] = make_int2((int32_t)A, q[j]);
+      else
+        ws.mover[A] = 1;
+    }
+  }
+}
 
 __global__ __launch_bounds__(256) void k_merge_cand(int S, MergeCuts m, TracksOut tr, FitsOut fits, Workspace ws,
                                                     int64_t n_max, int64_t pair_cap) {
   __shared__ float4 recs[kMergeTile];
   const int64_t n = min(tr.track_offset[S], n_max);
   const int lane = threadIdx.x & 63;
-  int64_t cbase = 0;      // the wave's current chunk
-  int used = kMergeChunk;  // entries of it taken (full: no chunk yet)
-  for (int s = blockIdx.x; s < S; s += gridDim.x) {
+  const int total = ws.mchunk[S];
+  for (int v = blockIdx.x; v < total; v += gridDim.x) {
+    // sector of this chunk of 256 segments: largest s with mchunk[s] <= v
+    int lo = 0, hi = S;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (ws.mchunk[mid] <= v) lo = mid; else hi = mid;
+    }
+    const int s = lo;
     const int64_t k0 = min(tr.track_offset[s], n), k1 = min(tr.track_offset[s + 1], n);
-    for (int64_t a0 = k0; a0 < k1; a0 += blockDim.x) {
-      const int64_t A = a0 + threadIdx.x;
-      int a_last = -1;
-      double ax = 0.0, ay = 0.0, az = 0.0, ty = 0.0, tz = 0.0;
-      if (A < k1) {
-        const int wa = __float_as_int(ws.mrec[A].w);
-        if (wa >= 0) {
-          a_last = wa >> 16;
-          ax = (double)fits.x[A];
-          ay = (double)fits.param[5 * A];
-          az = (double)fits.param[5 * A + 1];
-          const double as = (double)fits.param[5 * A + 2], al = (double)fits.param[5 * A + 3];
-          const double ca = sqrt(1.0 - as * as);
-          ty = as / ca;
-          tz = al / ca;
-        }
+    const int64_t A = k0 + (int64_t)(v - ws.mchunk[s]) * 256 + threadIdx.x;
+    int a_last = -1;
+    double ax = 0.0, ay = 0.0, az = 0.0, ty = 0.0, tz = 0.0;
+    if (A < k1) {
+      const int wa = __float_as_int(ws.mrec[A].w);
+      if (wa >= 0) {
+        a_last = wa >> 16;
+        ax = (double)fits.x[A];
+        ay = (double)fits.param[5 * A];
+        az = (double)fits.param[5 * A + 1];
+        const double as = (double)fits.param[5 * A + 2], al = (double)fits.param[5 * A + 3];
+        const double ca = sqrt(1.0 - as * as);
+        ty = as / ca;
+        tz = al / ca;
       }
-      for (int64_t b0 = k0; b0 < k1; b0 += kMergeTile) {
-        const int nb = (int)min<int64_t>(kMergeTile, k1 - b0);
-        __syncthreads();
-        for (int i = threadIdx.x; i < nb; i += blockDim.x) recs[i] = ws.mrec[b0 + i];
-        __syncthreads();
-        for (int i = 0; i < nb; ++i) {
-          const float4 rb = recs[i];
-          const int wb = __float_as_int(rb.w);
-          bool pass = false;
-          if (a_last >= 0 && wb >= 0 && b0 + i != A) {
-            const int b_first = wb & 0xffff;
-            if (b_first > a_last && b_first - a_last <= m.max_gap) {
-              const double dx0 = (double)rb.x - ax;
-              const double yw = (ay + dx0 * ty) - (double)rb.y;
-              const double zw = (az + dx0 * tz) - (double)rb.z;
-              pass = fabs(yw) <= m.window && fabs(zw) <= m.window;
-            }
+    }
+    int qn = 0;
+    int32_t q0 = -1, q1 = -1, q2 = -1, q3 = -1;
+    for (int64_t b0 = k0; b0 < k1; b0 += kMergeTile) {
+      const int nb = (int)min<int64_t>(kMergeTile, k1 - b0);
+      __syncthreads();
+      for (int i = threadIdx.x; i < nb; i += blockDim.x) recs[i] = ws.mrec[b0 + i];
+      __syncthreads();
+      for (int i = 0; i < nb; ++i) {
+        const float4 rb = recs[i];
+        const int wb = __float_as_int(rb.w);
+        bool pass = false;
+        if (a_last >= 0 && wb >= 0 && b0 + i != A) {
+          const int b_first = wb & 0xffff;
+          if (b_first > a_last && b_first - a_last <= m.max_gap) {
+            const double dx0 = (double)rb.x - ax;
+            const double yw = (ay + dx0 * ty) - (double)rb.y;
+            const double zw = (az + dx0 * tz) - (double)rb.z;
+            pass = fabs(yw) <= m.window && fabs(zw) <= m.window;
           }
-          const unsigned long long bal = __ballot(pass);
-          if (bal == 0ull) continue;
-          const int cnt = __popcll(bal);
-          const bool grab = used + cnt > kMergeChunk;
-          int64_t nbase = cbase;
-          if (grab) {
-            unsigned long long g = 0ull;
-            if (lane == 0) g = atomicAdd(&ws.counters[kCtrMergePairs], (unsigned long long)kMergeChunk);
-            const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)g, 0);
-            const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(g >> 32), 0);
-            nbase = (int64_t)(((unsigned long long)hi << 32) | lo);
-          }
-          if (pass) {
-            const int pos = used + __popcll(bal & ((1ull << lane) - 1ull));
-            const int64_t k = pos < kMergeChunk ? cbase + pos : nbase + (pos - kMergeChunk);
-            if (k < pair_cap)
-              ws.mpair[k] = make_int2((int32_t)A, (int32_t)(b0 + i));
-            else
-              ws.mover[A] = 1;
-          }
-          if (grab) {
-            cbase = nbase;
-            used = used + cnt - kMergeChunk;
-          } else {
-            used += cnt;
-          }
+        }
+        if (pass) {
+          q3 = q2;
+          q2 = q1;
+          q1 = q0;
+          q0 = (int32_t)(b0 + i);
+          ++qn;
+        }
+        if (__ballot(qn == kMergeQueue)) {
+          merge_flush(A, qn, q0, q1, q2, q3, lane, pair_cap, ws);
+          qn = 0;
         }
       }
     }
+    merge_flush(A, qn, q0, q1, q2, q3, lane, pair_cap, ws);
   }
-  if (used < kMergeChunk && lane >= used && cbase + lane < pair_cap) ws.mpair[cbase + lane] = make_int2(-1, -1);
 }
 
 // Segments marked by k_merge_cand evaluate all their pairs themselves (a
@@ -1693,9 +1738,7 @@ __global__ __launch_bounds__(256) void k_merge_over(int S, const float* __restri
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t A = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; A < n; A += stride) {
     if (!ws.mover[A]) continue;
-    merge_scan(A, n, S, m, tr, fits, ws, [&](int64_t B, int s) {
-      merge_pair(A, B, s, row_x, c, m, toff, trk, tr, fits, ws);
-    });
+    merge_scan(A, n, S, m, tr, fits, ws, [&](int64_t B, int) { merge_pair(A, B, row_x, c, m, trk, fits, ws); });
   }
 }
 
@@ -1707,9 +1750,7 @@ __global__ __launch_bounds__(256) void k_merge_chi2(int S, const float* __restri
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < np; k += stride) {
     const int2 ab = ws.mpair[k];
-    if (ab.x < 0) continue;  // padding of a wave's last chunk
-    const int s = sector_of(tr.track_offset, 0, S, ab.x);
-    merge_pair(ab.x, ab.y, s, row_x, c, m, toff, trk, tr, fits, ws);
+    merge_pair(ab.x, ab.y, row_x, c, m, trk, fits, ws);
   }
 }
 
@@ -2058,8 +2099,8 @@ hipError_t launch_merge(const Inputs& in, int S, int n_rows, const float* row_x,
   pair_cap = std::max<int64_t>(0, std::min(pair_cap, kMergePairsPerSlot * max_slots));
   hipLaunchKernelGGL(k_merge_prep, dim3(grid), dim3(256), 0, st, in, S, n_rows, toff, trk, trk_cap, tr, fits, out,
                      ws, n_max);
-  hipLaunchKernelGGL(k_merge_cand, dim3((unsigned)std::max(1, std::min(S, 8 * pair_grid))), dim3(256), 0, st, S, m, tr,
-                     fits, ws, n_max, pair_cap);
+  hipLaunchKernelGGL(k_merge_chunks, dim3(1), dim3(1024), 0, st, S, tr, ws, n_max);
+  hipLaunchKernelGGL(k_merge_cand, dim3((unsigned)pair_grid), dim3(256), 0, st, S, m, tr, fits, ws, n_max, pair_cap);
   hipLaunchKernelGGL(k_merge_chi2, dim3(pair_grid), dim3(256), 0, st, S, row_x, c, m, toff, trk, tr, fits, ws,
                      pair_cap);
   hipLaunchKernelGGL(k_merge_over, dim3(grid), dim3(256), 0, st, S, row_x, c, m, toff, trk, tr, fits, ws, n_max);
