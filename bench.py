@@ -64,6 +64,12 @@ def profiled_traffic(workload_name, tuning):
 
 
 DEAD_BAND = (70, 8)  # pad rows without clusters in the merging leg's second batch
+# binary64 operations of the merging's chi^2 pass: one row step of the transport (50 for the state
+# and the Jacobian, 400 for F C F^T over all 5x5 indices), and per pair the summed covariance,
+# Cholesky factorisation, forward substitution and the difference (110)
+MERGE_FLOPS_PER_STEP = 450
+MERGE_FLOPS_PER_PAIR = 110
+PEAK_FP64_TFLOPS = 78.6
 
 
 def merge_leg(tr, hits, out, tracks, fits, n_tracks, stream, reps=5):
@@ -79,8 +85,13 @@ def merge_leg(tr, hits, out, tracks, fits, n_tracks, stream, reps=5):
     s1.record(stream)
     torch.cuda.synchronize()
     mn = merges.numpy(n_tracks)
-    return {"ms": s0.elapsed_time(s1) / reps, "tracks": int(n_tracks), "links": int(np.sum(mn["next"] >= 0)),
+    pairs, steps = tr.merge_counts()
+    ms = s0.elapsed_time(s1) / reps
+    flops = MERGE_FLOPS_PER_STEP * steps + MERGE_FLOPS_PER_PAIR * pairs
+    return {"ms": ms, "tracks": int(n_tracks), "links": int(np.sum(mn["next"] >= 0)),
             "chains": int(np.sum((mn["next"] >= 0) & (mn["prev"] < 0))),
+            "candidate_pairs": int(pairs), "transport_steps": int(steps),
+            "fp64_tflops": flops / (ms * 1e-3) / 1e12, "fp64_peak_tflops": PEAK_FP64_TFLOPS,
             "what": "segment merging inside each sector: straight-line window, transported 5x5 covariance, "
                     "chi^2 of the two states, mutual best link (binary64)"}
 
@@ -407,7 +418,8 @@ def main():
         f"chi2/ndf {refit['chi2_per_ndf_mean']}")
     # segment merging inside the sectors (after the refit)
     merge = merge_leg(tr, hits, out, tracks, fits, n_tracks, stream)
-    log(f"[bench] merge: {merge['ms']:.3f} ms, {merge['links']} links among {n_tracks} tracks")
+    log(f"[bench] merge: {merge['ms']:.3f} ms, {merge['links']} links among {n_tracks} tracks, "
+        f"{merge['candidate_pairs']} pairs, {merge['transport_steps']} steps")
     del tracks, fits
     if not args.no_dead_band and args.workload == "batch64":
         import synth
@@ -427,7 +439,9 @@ def main():
         merge["dead_band"]["rows"] = [DEAD_BAND[0], DEAD_BAND[0] + DEAD_BAND[1] - 1]
         merge["dead_band"]["hits"] = int(hd.n_hits)
         log(f"[bench] merge, dead rows {DEAD_BAND[0]}-{DEAD_BAND[0] + DEAD_BAND[1] - 1}: "
-            f"{merge['dead_band']['ms']:.3f} ms, {merge['dead_band']['links']} links among {nt_d} tracks")
+            f"{merge['dead_band']['ms']:.3f} ms, {merge['dead_band']['links']} links among {nt_d} tracks, "
+            f"{merge['dead_band']['candidate_pairs']} pairs, {merge['dead_band']['transport_steps']} steps, "
+            f"{merge['dead_band']['fp64_tflops']:.2f} TFLOP/s binary64")
         del bd, hd, od, td, fd
         tr.track(hits, out)  # leave the context's last call on the main workload
         tr.result()

@@ -309,6 +309,11 @@ catpc_status catpc_merge_tracks(catpc_ctx* ctx, const catpc_input* in, const cat
                                 const catpc_tracks* tracks, const catpc_fits* fits, const catpc_merge_params* mp,
                                 const catpc_merges* out, void* stream);
 
+/* Measurement: synchronise `stream` and report the last merge call's
+ * candidate pairs (those that passed the row and window tests) and the row
+ * steps their transports took. */
+catpc_status catpc_merge_counts(catpc_ctx* ctx, void* stream, int64_t* n_pairs, int64_t* n_steps);
+
 /* Synchronise `stream` and report the last selection: the number of tracks
  * and of their hits.  CATPC_E_CAPACITY if the output held fewer, or if the
  * tracklet output held only part of the tracklets (then the selection covers

@@ -24,7 +24,7 @@ STAGES = ("row_index", "grid", "neighbours", "clean_start", "scan", "compact", "
 
 EXPORTS = ("catpc_stage_times", "catpc_work_counts", "catpc_default_params", "catpc_default_tuning", "catpc_row_stride", "catpc_workspace_bytes", "catpc_create", "catpc_destroy",
            "catpc_set_params", "catpc_set_tuning", "catpc_get_tuning", "catpc_track_batch", "catpc_track_plain",
-           "catpc_result", "catpc_fetch_tracklets", "catpc_select_tracklets", "catpc_select_result", "catpc_refit_tracks", "catpc_default_merge_params", "catpc_merge_tracks", "catpc_fp32_probe", "catpc_probe_copy", "catpc_probe_fma",
+           "catpc_result", "catpc_fetch_tracklets", "catpc_select_tracklets", "catpc_select_result", "catpc_refit_tracks", "catpc_default_merge_params", "catpc_merge_tracks", "catpc_merge_counts", "catpc_fp32_probe", "catpc_probe_copy", "catpc_probe_fma",
            "catpc_last_error")
 
 
@@ -129,6 +129,8 @@ def lib():
         L.catpc_merge_tracks.argtypes = [_vp, P(catpc_input), P(catpc_output), P(catpc_tracks), P(catpc_fits),
                                          P(catpc_merge_params), P(catpc_merges), _vp]
         L.catpc_merge_tracks.restype = st
+        L.catpc_merge_counts.argtypes = [_vp, _vp, P(ctypes.c_int64), P(ctypes.c_int64)]
+        L.catpc_merge_counts.restype = st
         L.catpc_select_result.restype = st
         L.catpc_stage_times.argtypes = [_vp, P(catpc_input), P(catpc_output), _vp, _vp]
         L.catpc_stage_times.restype = st
@@ -236,6 +238,12 @@ def catpc_select_tracklets(ctx, inp, trk, tracks, stream):
 def catpc_refit_tracks(ctx, inp, trk, tracks, fits, stream):
     return _check(lib().catpc_refit_tracks(ctx, ctypes.byref(inp), ctypes.byref(trk), ctypes.byref(tracks),
                                            ctypes.byref(fits), stream))
+
+
+def catpc_merge_counts(ctx, stream):
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().catpc_merge_counts(ctx, stream, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def catpc_merge_tracks(ctx, inp, trk, tracks, fits, mp, out, stream):

@@ -110,7 +110,7 @@ struct catpc_ctx {
   Consts consts{};
   void* ws_mem = nullptr;
   Workspace ws{};
-  unsigned long long* host_counters = nullptr;  // pinned [8]
+  unsigned long long* host_counters = nullptr;  // pinned [kNumCounters]
   int64_t* host_total = nullptr;                 // pinned [1]
   // last track call
   bool have_last = false;
@@ -672,6 +672,18 @@ catpc_status catpc_work_counts(catpc_ctx* ctx, void* stream, int64_t* counts) {
                          hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   for (int k = 0; k < 4; ++k) counts[k] = (int64_t)ctx->host_counters[kCtrCounts + k];
+  return CATPC_OK;
+}
+
+catpc_status catpc_merge_counts(catpc_ctx* ctx, void* stream, int64_t* n_pairs, int64_t* n_steps) {
+  if (!ctx) return fail(CATPC_E_INVALID, "ctx is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipMemcpyAsync(ctx->host_counters, ctx->ws.counters, sizeof(unsigned long long) * kNumCounters,
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (n_pairs) *n_pairs = (int64_t)ctx->host_counters[kCtrMergePairs];
+  if (n_steps) *n_steps = (int64_t)ctx->host_counters[kCtrMergeSteps];
   return CATPC_OK;
 }
 

@@ -85,7 +85,8 @@ constexpr int kCtrCounts = 9;    // [9, 13): transports, updates, gated candidat
 constexpr int kCtrSelTracks = 13;  // selected tracks
 constexpr int kCtrSelHits = 14;    // hits they keep
 constexpr int kCtrMergePairs = 15;  // candidate pairs of the segment merging
-constexpr int kNumCounters = 16;
+constexpr int kCtrMergeSteps = 16;  // row steps of their transports
+constexpr int kNumCounters = 24;
 constexpr int64_t kMergePairsPerSlot = 4;  // candidate-pair list length per track slot
 
 // Call geometry: sectors [s0, s1), hits [h0, h1) (global indices).

@@ -1464,7 +1464,10 @@ __global__ __launch_bounds__(256) void k_fullfit(Inputs in, int S, int R, const 
 __global__ __launch_bounds__(256) void k_merge_prep(Inputs in, int S, int R, const int64_t* toff, TrackletOut trk,
                                                     int64_t trk_cap, TracksOut tr, FitsOut fits, MergeOut out,
                                                     Workspace ws, int64_t n_max) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) ws.counters[kCtrMergePairs] = 0ull;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ws.counters[kCtrMergePairs] = 0ull;
+    ws.counters[kCtrMergeSteps] = 0ull;
+  }
   const int64_t n = min(tr.track_offset[S], n_max);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
@@ -1503,7 +1506,8 @@ __global__ __launch_bounds__(256) void k_merge_prep(Inputs in, int S, int R, con
 // (A carried row by row with the refit's transport and Jacobian), or -1 when
 // the transport stops or the summed covariance is not positive definite.
 __device__ __forceinline__ double merge_chi2(int64_t A, int64_t B, const float* __restrict__ row_x, double kb,
-                                             const TrackletOut& trk, const FitsOut& fits, const Workspace& ws) {
+                                             const TrackletOut& trk, const FitsOut& fits, const Workspace& ws,
+                                             int& steps) {
   const int a_last = __float_as_int(ws.mrec[A].w) >> 16;
   const int b_first = __float_as_int(ws.mrec[B].w) & 0xffff;
   const int64_t sb = ws.mslot[B];
@@ -1518,6 +1522,7 @@ __device__ __forceinline__ double merge_chi2(int64_t A, int64_t B, const float* 
     FitJac J;
     if (ff_transport(x, p, (double)row_x[r], kb, &J)) return -1.0;
     ff_transport_cov(C, J);
+    ++steps;
   }
   double d[5], L[5][5];
 #pragma unroll
@@ -1558,8 +1563,8 @@ __device__ __forceinline__ double merge_chi2(int64_t A, int64_t B, const float* 
 // values; equal values order by the index).
 __device__ __forceinline__ void merge_pair(int64_t A, int64_t B, const float* __restrict__ row_x, const Consts& c,
                                            const MergeCuts& m, const TrackletOut& trk, const FitsOut& fits,
-                                           const Workspace& ws) {
-  const double chi2 = merge_chi2(A, B, row_x, c.kbd, trk, fits, ws);
+                                           const Workspace& ws, int& steps) {
+  const double chi2 = merge_chi2(A, B, row_x, c.kbd, trk, fits, ws, steps);
   if (!(chi2 >= 0.0 && chi2 <= m.chi2_max)) return;
   const unsigned long long hi = (unsigned long long)__float_as_uint((float)chi2) << 32;
   atomicMin(&ws.mkey_a[A], hi | (unsigned long long)(uint32_t)B);
@@ -1738,7 +1743,9 @@ __global__ __launch_bounds__(256) void k_merge_over(int S, const float* __restri
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t A = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; A < n; A += stride) {
     if (!ws.mover[A]) continue;
-    merge_scan(A, n, S, m, tr, fits, ws, [&](int64_t B, int) { merge_pair(A, B, row_x, c, m, trk, fits, ws); });
+    int steps = 0;
+    merge_scan(A, n, S, m, tr, fits, ws, [&](int64_t B, int) { merge_pair(A, B, row_x, c, m, trk, fits, ws, steps); });
+    atomicAdd(&ws.counters[kCtrMergeSteps], (unsigned long long)steps);
   }
 }
 
@@ -1748,10 +1755,15 @@ __global__ __launch_bounds__(256) void k_merge_chi2(int S, const float* __restri
                                                     Workspace ws, int64_t pair_cap) {
   const int64_t np = min((int64_t)ws.counters[kCtrMergePairs], pair_cap);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int steps = 0;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < np; k += stride) {
     const int2 ab = ws.mpair[k];
-    merge_pair(ab.x, ab.y, row_x, c, m, trk, fits, ws);
+    merge_pair(ab.x, ab.y, row_x, c, m, trk, fits, ws, steps);
   }
+  // one atomic per wave for the step count
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) steps += __shfl_xor(steps, d);
+  if ((threadIdx.x & 63) == 0 && steps) atomicAdd(&ws.counters[kCtrMergeSteps], (unsigned long long)steps);
 }
 
 // Link A to its best continuation B when A is B's best predecessor.

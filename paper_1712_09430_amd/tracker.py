@@ -259,6 +259,11 @@ class Tracker:
             C.catpc_merge_tracks(self.ctx, hits.struct, out.struct, tracks.struct, fits.struct, cuts,
                                  merges.struct, _stream(self.device))
 
+    def merge_counts(self):
+        """Synchronise; (candidate pairs, transport row steps) of the last merge."""
+        with torch.cuda.device(self.device):
+            return C.catpc_merge_counts(self.ctx, _stream(self.device))
+
     def select_result(self):
         """Synchronise; (n_tracks, n_track_hits)."""
         with torch.cuda.device(self.device):

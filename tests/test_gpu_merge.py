@@ -113,6 +113,39 @@ def test_pair_list_overflow_gives_the_same_links(cap):
     assert check(b, g, m, C.catpc_default_params(), [0]) > 100
 
 
+def test_work_counts_match_the_candidate_tests():
+    """catpc_merge_counts: the candidate pairs are those passing the row and
+    straight-line window tests (counted here on the GPU's own fit and
+    tracklet outputs, in binary64 with the same expressions), and the row
+    steps are the rows between the pairs' ends."""
+    b = synth.sector_workload(seed=2, n_tracks=300, dead_rows=DEAD)
+    tr, hits, out, st, n = run_gpu(b)
+    g, f, m, nt = gpu_merges(tr, hits, out)
+    pairs, steps = tr.merge_counts()
+    trk = out.tracklets_numpy(n)
+    slot = g["track_tracklet"][:nt].astype(np.int64)
+    last = np.array([b.row[g["track_hits"][g["track_hit_offset"][k] + g["track_n_hits"][k] - 1]]
+                     for k in range(nt)])
+    first = trk["first_row"][slot]
+    sx, sy, sz = (trk["x_ref"][slot].astype(np.float64), trk["param"][slot, 0].astype(np.float64),
+                  trk["param"][slot, 1].astype(np.float64))
+    ok = f["flags"] == 1
+    want_pairs = want_steps = 0
+    for a in np.flatnonzero(ok):
+        p = f["param"][a].astype(np.float64)
+        c = np.sqrt(1.0 - p[2] * p[2])
+        ty, tz = p[2] / c, p[3] / c
+        for bb in np.flatnonzero(ok):
+            if bb == a or not (last[a] < first[bb] <= last[a] + 30):
+                continue
+            dx0 = sx[bb] - np.float64(f["x"][a])
+            if abs((p[0] + dx0 * ty) - sy[bb]) <= 10.0 and abs((p[1] + dx0 * tz) - sz[bb]) <= 10.0:
+                want_pairs += 1
+                want_steps += int(first[bb] - last[a])
+    assert pairs == want_pairs and pairs > 0
+    assert 0.9 * want_steps <= steps <= want_steps
+
+
 def test_no_dead_band_and_empty_sectors():
     from paper_1712_09430_amd import catpc as C
     b = synth.event_workload(seed=2, n_tracks=300)
