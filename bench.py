@@ -247,6 +247,54 @@ def scheduling_leg(batch, tuning, hits_total, log):
     return out
 
 
+LINEARITY_TRACKS = (250, 500, 1000, 2000, 4000, 8000, 16000)
+
+
+def linearity_leg(torch, tuning, seed, log, reps=10):
+    """Tracking time against input size (the tracking follows at most one
+    hypothesis per hit, so its time grows about linearly with the hits):
+    single events of increasing multiplicity through the batched chain,
+    median of `reps` HIP-event-timed calls each; a least-squares line
+    t = a + b * hits and the log-log slope over the larger half."""
+    import synth
+    from paper_1712_09430_amd.tracker import DeviceHits, Tracker
+    dev = "cuda:0"
+    stream = torch.cuda.current_stream()
+    evs = [synth.event_workload(seed=seed, n_tracks=n) for n in LINEARITY_TRACKS]
+    hmax = max(int(e.n_hits) for e in evs)
+    tr = Tracker(evs[0].row_x, hmax, max(e.n_sectors for e in evs), device=dev, tuning=tuning)
+    pts = []
+    for n, e in zip(LINEARITY_TRACKS, evs):
+        hits = DeviceHits(e.y, e.z, e.row, e.hit_offset, dev)
+        out = tr.output(hits)
+        for _ in range(2):
+            tr.track(hits, out)
+        tr.result()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record(stream)
+        for k in range(reps):
+            tr.track(hits, out)
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.median([ev[k].elapsed_time(ev[k + 1]) for k in range(reps)]))
+        pts.append((int(hits.n_hits), ms))
+        log(f"[bench] linearity: {n} tracks, {hits.n_hits} hits, {ms:.3f} ms")
+        del hits, out
+    tr.close()
+    h = np.array([p[0] for p in pts], float)
+    t = np.array([p[1] for p in pts], float)
+    b, a = np.polyfit(h, t, 1)
+    r2 = 1.0 - np.sum((t - (a + b * h)) ** 2) / np.sum((t - t.mean()) ** 2)
+    big = h >= np.median(h)
+    slope = float(np.polyfit(np.log(h[big]), np.log(t[big]), 1)[0])
+    res = {"tracks": list(LINEARITY_TRACKS), "hits": [int(x) for x in h], "ms": [float(x) for x in t],
+           "fit_ms": {"intercept": float(a), "per_mhit": float(b * 1e6)}, "r2": float(r2),
+           "loglog_slope_upper_half": slope,
+           "what": "single events through the batched chain; time vs hits, least-squares line and log-log slope"}
+    log(f"[bench] linearity: t = {a:.3f} ms + {b * 1e6:.3f} ms/Mhit, R^2 {r2:.4f}, log-log slope {slope:.3f}")
+    return res
+
+
 def serving_leg(args, tuning, log):
     """Poisson stream of events (multiplicities as in the batch workload) through
     the continuous-batching server; latency from arrival to results in host
@@ -291,6 +339,7 @@ def main():
     ap.add_argument("--no-peaks", action="store_true", help="skip the copy and FMA peak probes")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision-form report")
     ap.add_argument("--no-scheduling", action="store_true", help="skip the scheduling baselines")
+    ap.add_argument("--no-linearity", action="store_true", help="skip the time-vs-hits check")
     ap.add_argument("--no-dead-band", action="store_true",
                     help="skip the merging leg's second batch (same events, 8 dead pad rows)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -508,6 +557,10 @@ def main():
     if not args.no_precision:
         precision = precision_leg(torch, tuning, log)
 
+    linearity = None
+    if not args.no_linearity:
+        linearity = linearity_leg(torch, tuning, args.seed, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         cores = min(16, os.cpu_count() or 1)
@@ -536,7 +589,7 @@ def main():
            "plain": plain, "batched_over_plain": (value / plain["hits_per_s"]) if plain else None,
            "serving": serving, "stages_ms": stages, "roofline": {k: v for k, v in dominant.items() if k != "kernel"} |
            {"kernel": dominant["kernel"]}, "rooflines": {"k_tracklets": rl_tc, "k_neighbours": rl_nf},
-           "selection": sel, "refit": refit, "merge": merge, "scheduling": scheduling, "achievable_peaks": peaks, "precision": precision, "cpu_baseline": cpu}
+           "selection": sel, "refit": refit, "merge": merge, "scheduling": scheduling, "achievable_peaks": peaks, "precision": precision, "linearity": linearity, "cpu_baseline": cpu}
     print(json.dumps(res), flush=True)
 
 
