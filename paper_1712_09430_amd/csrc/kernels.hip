@@ -265,67 +265,32 @@ struct Stage {
   bool on;
 };
 
+// kLds: every row the block reads is staged, and the pointers lead only to
+// LDS, so the compiler emits LDS reads; otherwise they lead only to global
+// memory.  (A pointer that may lead to either becomes a flat access, which
+// is slower for both.)
+template <bool kLds>
 __device__ __forceinline__ RowGrid staged_grid(const Workspace& ws, int R, int s, int rr, const Stage& S) {
   RowGrid G = row_grid(ws, R, s, rr);
-  if (S.on && rr >= S.r_lo && rr <= S.r_hi) {
+  if (kLds) {
     G.hits = S.hits + (G.hits - (ws.sorted + S.hit0));
     G.bins = S.bins + (G.bins - (ws.bins + S.bin0));
   }
   return G;
 }
 
-// One workgroup per (sector, chunk of `rows` pad rows); its lanes take the
-// chunk's hits in grid order (all rows of the chunk together, so sparse rows
-// do not leave lanes idle).  The chunk's rows and the row on each side are
-// contiguous in the grid-sorted array and in the bin tables; they are staged
-// in LDS when they fit in `lds_bytes` (dynamic shared memory), else read in
-// place.  Down-row candidates inside the window are kept in registers (up to
-// kNfKeep; beyond that the down row is scanned again per up candidate).  Hits
-// of rows 0 and R-1 get -1 links.  rowk[r] = (x_{r+1}/x_r, x_{r-1}/x_r,
-// (x_r - x_{r-1}) / (x_{r+1} - x_{r-1})), each one binary32 division.
-__global__ __launch_bounds__(256) void k_neighbours(Inputs in, Span sp, int R, const float4* __restrict__ rowk,
-                                                    Consts c, Workspace ws, int32_t* __restrict__ out_up,
-                                                    int32_t* __restrict__ out_dn, int rows, int lds_bytes) {
-  extern __shared__ __align__(16) unsigned char lds[];
-  const int chunks = (R + rows - 1) / rows;
-  const int s = sp.s0 + (int)(blockIdx.x / chunks);
-  const int c0 = (int)(blockIdx.x % chunks) * rows;
-  const int c1 = min(R, c0 + rows);
-  const int32_t* rf = ws.row_first + (int64_t)s * (R + 1);
-  const int n = rf[c1] - rf[c0];
-  if (n <= 0) return;
-  const int64_t a = in.hit_offset[s];
-  Stage S;
-  S.on = false;
-  S.r_lo = max(c0 - 1, 0);
-  S.r_hi = min(c1, R - 1);
-  const SortedHit* own = ws.sorted + a + rf[c0];
-  {
-    const int64_t h0 = a + rf[S.r_lo], h1 = a + rf[S.r_hi + 1];
-    const int64_t b0 = 2 * (h0 + (int64_t)s * R + S.r_lo);
-    const int64_t b1 = 2 * (h1 + (int64_t)s * R + S.r_hi + 1);
-    const int64_t nh = h1 - h0, nb = b1 - b0;
-    if (nh * (int64_t)sizeof(SortedHit) + nb * (int64_t)sizeof(int32_t) <= lds_bytes) {
-      SortedHit* lh = reinterpret_cast<SortedHit*>(lds);
-      int32_t* lb = reinterpret_cast<int32_t*>(lds + nh * sizeof(SortedHit));
-      for (int k = threadIdx.x; k < nh; k += blockDim.x) lh[k] = ws.sorted[h0 + k];
-      for (int k = threadIdx.x; k < nb; k += blockDim.x) lb[k] = ws.bins[b0 + k];
-      __syncthreads();
-      S.on = true;
-      S.hit0 = h0;
-      S.bin0 = b0;
-      S.hits = lh;
-      S.bins = lb;
-      own = lh + (a + rf[c0] - h0);
-    }
-  }
+// The neighbour search of the block's hits (`own`, n of them, grid order).
+template <bool kLds>
+__device__ __forceinline__ void nf_hits(const SortedHit* own, int n, int64_t a, int s, int R,
+                                        const float4* __restrict__ rowk, const Consts& c, const Workspace& ws,
+                                        const Stage& S, int32_t* __restrict__ out_up, int32_t* __restrict__ out_dn) {
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
     const SortedHit me = own[k];
     const int r = me.row;
     int32_t bj = -1, bk = -1;
     if (r >= 1 && r <= R - 2) {
-      const RowGrid U = staged_grid(ws, R, s, r + 1, S);
-      const RowGrid D = staged_grid(ws, R, s, r - 1, S);
+      const RowGrid U = staged_grid<kLds>(ws, R, s, r + 1, S);
+      const RowGrid D = staged_grid<kLds>(ws, R, s, r - 1, S);
       if (U.ny > 0 && D.ny > 0) {
         const float4 f = rowk[r];
         const float fu = f.x, fd = f.y, t = f.z;
@@ -380,6 +345,55 @@ __global__ __launch_bounds__(256) void k_neighbours(Inputs in, Span sp, int R, c
     out_up[i] = bj;
     out_dn[i] = bk;
   }
+}
+
+// One workgroup per (sector, chunk of `rows` pad rows); its lanes take the
+// chunk's hits in grid order (all rows of the chunk together, so sparse rows
+// do not leave lanes idle).  The chunk's rows and the row on each side are
+// contiguous in the grid-sorted array and in the bin tables; they are staged
+// in LDS when they fit in `lds_bytes` (dynamic shared memory), else read in
+// place.  Down-row candidates inside the window are kept in registers (up to
+// kNfKeep; beyond that the down row is scanned again per up candidate).  Hits
+// of rows 0 and R-1 get -1 links.  rowk[r] = (x_{r+1}/x_r, x_{r-1}/x_r,
+// (x_r - x_{r-1}) / (x_{r+1} - x_{r-1})), each one binary32 division.
+__global__ __launch_bounds__(256) void k_neighbours(Inputs in, Span sp, int R, const float4* __restrict__ rowk,
+                                                    Consts c, Workspace ws, int32_t* __restrict__ out_up,
+                                                    int32_t* __restrict__ out_dn, int rows, int lds_bytes) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int chunks = (R + rows - 1) / rows;
+  const int s = sp.s0 + (int)(blockIdx.x / chunks);
+  const int c0 = (int)(blockIdx.x % chunks) * rows;
+  const int c1 = min(R, c0 + rows);
+  const int32_t* rf = ws.row_first + (int64_t)s * (R + 1);
+  const int n = rf[c1] - rf[c0];
+  if (n <= 0) return;
+  const int64_t a = in.hit_offset[s];
+  Stage S;
+  S.on = false;
+  S.r_lo = max(c0 - 1, 0);
+  S.r_hi = min(c1, R - 1);
+  {
+    const int64_t h0 = a + rf[S.r_lo], h1 = a + rf[S.r_hi + 1];
+    const int64_t b0 = 2 * (h0 + (int64_t)s * R + S.r_lo);
+    const int64_t b1 = 2 * (h1 + (int64_t)s * R + S.r_hi + 1);
+    const int64_t nh = h1 - h0, nb = b1 - b0;
+    if (nh * (int64_t)sizeof(SortedHit) + nb * (int64_t)sizeof(int32_t) <= lds_bytes) {
+      SortedHit* lh = reinterpret_cast<SortedHit*>(lds);
+      int32_t* lb = reinterpret_cast<int32_t*>(lds + nh * sizeof(SortedHit));
+      for (int k = threadIdx.x; k < nh; k += blockDim.x) lh[k] = ws.sorted[h0 + k];
+      for (int k = threadIdx.x; k < nb; k += blockDim.x) lb[k] = ws.bins[b0 + k];
+      __syncthreads();
+      S.on = true;
+      S.hit0 = h0;
+      S.bin0 = b0;
+      S.hits = lh;
+      S.bins = lb;
+    }
+  }
+  if (S.on)
+    nf_hits<true>(S.hits + (a + rf[c0] - S.hit0), n, a, s, R, rowk, c, ws, S, out_up, out_dn);
+  else
+    nf_hits<false>(ws.sorted + a + rf[c0], n, a, s, R, rowk, c, ws, S, out_up, out_dn);
 }
 
 // -------------------------------------------------------------- clean/start
