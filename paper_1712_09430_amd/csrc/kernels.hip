@@ -668,6 +668,8 @@ struct Pick {
   float y, z;
 };
 
+constexpr int kClosestRows = 2;  // z rows of a search whose bin ranges are loaded up front
+
 // Closest gated cluster of a row: smallest dy^2 + dz^2, ties to the smaller
 // sector-local index.
 __device__ __forceinline__ Pick closest(const Trk& t, const RowGrid& G, const Consts& c, Work& w) {
@@ -678,22 +680,43 @@ __device__ __forceinline__ Pick closest(const Trk& t, const RowGrid& G, const Co
   if (G.ny <= 0) return best;
   const BinRange br = bin_range(G, t.y, gy, t.z, gz);
   float bd = 0.0f;
-  for (int iz = br.z0; iz <= br.z1; ++iz) {
-    const int pe = G.bins[iz * G.ny + br.y1 + 1];
-    for (int p = G.bins[iz * G.ny + br.y0]; p < pe; ++p) {
-      const SortedHit h = G.hits[p];
-      const float dy = h.y - t.y;
-      const float dz = h.z - t.z;
-      if (!(fabsf(dy) <= gy && fabsf(dz) <= gz)) continue;
-      ++w.n_cand;
-      const float d2 = dy * dy + dz * dz;
-      if (best.idx < 0 || d2 < bd || (d2 == bd && h.idx < best.idx)) {
-        best.idx = h.idx;
-        best.y = h.y;
-        best.z = h.z;
-        bd = d2;
-      }
+  auto take = [&](const SortedHit& h) {
+    const float dy = h.y - t.y;
+    const float dz = h.z - t.z;
+    if (!(fabsf(dy) <= gy && fabsf(dz) <= gz)) return;
+    ++w.n_cand;
+    const float d2 = dy * dy + dz * dz;
+    if (best.idx < 0 || d2 < bd || (d2 == bd && h.idx < best.idx)) {
+      best.idx = h.idx;
+      best.y = h.y;
+      best.z = h.z;
+      bd = d2;
     }
+  };
+  // The bin ranges of the first kClosestRows z rows are loaded together (one
+  // memory round trip instead of one per row), and candidates are read two at
+  // a time.  The result is the minimum of (d2, index) whatever the order.
+  int ps[kClosestRows], pe[kClosestRows];
+#pragma unroll
+  for (int q = 0; q < kClosestRows; ++q) {
+    const int iz = min(br.z0 + q, br.z1);
+    ps[q] = G.bins[iz * G.ny + br.y0];
+    pe[q] = G.bins[iz * G.ny + br.y1 + 1];
+    if (br.z0 + q > br.z1) pe[q] = ps[q];
+  }
+#pragma unroll
+  for (int q = 0; q < kClosestRows; ++q) {
+    int p = ps[q];
+    for (; p + 1 < pe[q]; p += 2) {
+      const SortedHit h0 = G.hits[p], h1 = G.hits[p + 1];
+      take(h0);
+      take(h1);
+    }
+    if (p < pe[q]) take(G.hits[p]);
+  }
+  for (int iz = br.z0 + kClosestRows; iz <= br.z1; ++iz) {
+    const int e = G.bins[iz * G.ny + br.y1 + 1];
+    for (int p = G.bins[iz * G.ny + br.y0]; p < e; ++p) take(G.hits[p]);
   }
   return best;
 }
