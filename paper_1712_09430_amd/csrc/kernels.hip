@@ -237,6 +237,35 @@ __device__ __forceinline__ BinRange bin_range(const RowGrid& G, float yc, float 
   return b;
 }
 
+// f(hit) for every hit in the bins [y0, y1] of the z rows [z0, z1] of G: the
+// bin ranges of the first kFront rows are loaded together (one memory round
+// trip instead of one per row) and hits are read two at a time.
+template <int kFront, class F>
+__device__ __forceinline__ void for_hits(const RowGrid& G, const BinRange& br, F&& f) {
+  int ps[kFront], pe[kFront];
+#pragma unroll
+  for (int q = 0; q < kFront; ++q) {
+    const int iz = min(br.z0 + q, br.z1);
+    ps[q] = G.bins[iz * G.ny + br.y0];
+    pe[q] = G.bins[iz * G.ny + br.y1 + 1];
+    if (br.z0 + q > br.z1) pe[q] = ps[q];
+  }
+#pragma unroll
+  for (int q = 0; q < kFront; ++q) {
+    int p = ps[q];
+    for (; p + 1 < pe[q]; p += 2) {
+      const SortedHit h0 = G.hits[p], h1 = G.hits[p + 1];
+      f(h0);
+      f(h1);
+    }
+    if (p < pe[q]) f(G.hits[p]);
+  }
+  for (int iz = br.z0 + kFront; iz <= br.z1; ++iz) {
+    const int e = G.bins[iz * G.ny + br.y1 + 1];
+    for (int p = G.bins[iz * G.ny + br.y0]; p < e; ++p) f(G.hits[p]);
+  }
+}
+
 constexpr int kNfKeep = 8;
 
 // Score the pair (up j, down k) for the hit (yi, zi) and keep the
@@ -693,31 +722,8 @@ __device__ __forceinline__ Pick closest(const Trk& t, const RowGrid& G, const Co
       bd = d2;
     }
   };
-  // The bin ranges of the first kClosestRows z rows are loaded together (one
-  // memory round trip instead of one per row), and candidates are read two at
-  // a time.  The result is the minimum of (d2, index) whatever the order.
-  int ps[kClosestRows], pe[kClosestRows];
-#pragma unroll
-  for (int q = 0; q < kClosestRows; ++q) {
-    const int iz = min(br.z0 + q, br.z1);
-    ps[q] = G.bins[iz * G.ny + br.y0];
-    pe[q] = G.bins[iz * G.ny + br.y1 + 1];
-    if (br.z0 + q > br.z1) pe[q] = ps[q];
-  }
-#pragma unroll
-  for (int q = 0; q < kClosestRows; ++q) {
-    int p = ps[q];
-    for (; p + 1 < pe[q]; p += 2) {
-      const SortedHit h0 = G.hits[p], h1 = G.hits[p + 1];
-      take(h0);
-      take(h1);
-    }
-    if (p < pe[q]) take(G.hits[p]);
-  }
-  for (int iz = br.z0 + kClosestRows; iz <= br.z1; ++iz) {
-    const int e = G.bins[iz * G.ny + br.y1 + 1];
-    for (int p = G.bins[iz * G.ny + br.y0]; p < e; ++p) take(G.hits[p]);
-  }
+  // the result is the minimum of (d2, index) whatever the order of the hits
+  for_hits<kClosestRows>(G, br, take);
   return best;
 }
 
