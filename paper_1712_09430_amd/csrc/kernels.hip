@@ -868,7 +868,7 @@ __device__ __forceinline__ int wave_max16(int v) {
 // starts later waits), so that they read the same row grids at the same time;
 // each lane's own sequence of filter steps is the same either way.
 template <bool kSync>
-__device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __restrict__ row_x, const Consts& c,
+__device__ __forceinline__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __restrict__ row_x, const Consts& c,
                                const Workspace& ws, const int64_t* toff, int64_t slot, int64_t o,
                                const TrackletOut& out, int RS, int32_t* chunk_lds, Work& w) {
   const int s = sector_of(toff, sp.s0, sp.s1, slot);
@@ -879,6 +879,11 @@ __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __
   const ChainHit c0 = ws.chain[gi];
   const int32_t h1 = c0.up;
   ChainHit nx = ws.chain[a + h1];  // next chain measurement
+  // the one after it, read one row step ahead so that the pointer chase
+  // along the chain overlaps a step of filter arithmetic (a start hit always
+  // has an up-link of its up-link)
+  ChainHit nn = nx;
+  if (nx.up >= 0) nn = ws.chain[a + nx.up];
   int32_t* rec = out.row_hit + o * RS;
   const int k0 = r0 >> 3;  // chunk of the start row
   RowChunk k = {chunk_lds + threadIdx.x, (int)blockDim.x, k0};
@@ -927,7 +932,10 @@ __device__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __
         miss = 0;
         if (h >= 0) {
           h = nx.up;
-          if (h >= 0) nx = ws.chain[a + h];
+          if (h >= 0) {
+            nx = nn;
+            if (nx.up >= 0) nn = ws.chain[a + nx.up];
+          }
         }
       } else if (++miss > c.max_miss) {
         break;
@@ -999,6 +1007,12 @@ __global__ __launch_bounds__(kTcMaxBlock) __attribute__((amdgpu_waves_per_eu(kWa
 k_tracklets(Inputs in, Span sp, int R, const float* __restrict__ row_x, Consts c, Workspace ws, const int64_t* toff,
             int64_t first, int64_t cap, TrackletOut out, int nparts) {
   __shared__ int32_t chunk_lds[8 * kTcMaxBlock];
+  // the pad-row planes in LDS (dynamic, R floats): LDS reads do not wait
+  // behind the lane's outstanding memory loads as global reads would
+  extern __shared__ __align__(16) unsigned char tc_dyn[];
+  float* rxs = reinterpret_cast<float*>(tc_dyn);
+  for (int i = threadIdx.x; i < R; i += blockDim.x) rxs[i] = row_x[i];
+  __syncthreads();
   const int64_t lo = max(toff[sp.s0], first);
   const int64_t hi = min(toff[sp.s1], first + cap);
   const int lane = threadIdx.x & 63;
@@ -1010,7 +1024,7 @@ k_tracklets(Inputs in, Span sp, int R, const float* __restrict__ row_x, Consts c
     const int64_t slot0 = take_slots(P, k, ws.counters + kCtrWork, 64, lane, pend);
     if (slot0 < 0) break;
     const int64_t slot = slot0 + lane;
-    if (slot < pend) build_tracklet<kSync>(in, sp, R, row_x, c, ws, toff, slot, slot - first, out, row_stride(R), chunk_lds,
+    if (slot < pend) build_tracklet<kSync>(in, sp, R, rxs, c, ws, toff, slot, slot - first, out, row_stride(R), chunk_lds,
                                              w);
   }
   flush_work(w, ws, lane);
@@ -2104,10 +2118,12 @@ hipError_t launch_tracklets(const Inputs& in, Span sp, int n_rows, const float* 
 #define CATPC_TC(K)                                                                                           \
   do {                                                                                                        \
     if (sync)                                                                                                 \
-      hipLaunchKernelGGL((k_tracklets<K, true>), dim3(grid), dim3(block), 0, st, in, sp, n_rows, row_x, c, ws,   \
+      hipLaunchKernelGGL((k_tracklets<K, true>), dim3(grid), dim3(block), n_rows * sizeof(float), st, in, sp,     \
+                         n_rows, row_x, c, ws,                                                                \
                          toff, first, cap, out, nparts);                                                      \
     else                                                                                                      \
-      hipLaunchKernelGGL((k_tracklets<K, false>), dim3(grid), dim3(block), 0, st, in, sp, n_rows, row_x, c, ws,  \
+      hipLaunchKernelGGL((k_tracklets<K, false>), dim3(grid), dim3(block), n_rows * sizeof(float), st, in, sp,    \
+                         n_rows, row_x, c, ws,                                                                \
                          toff, first, cap, out, nparts);                                                      \
   } while (0)
   switch (waves) {
