@@ -71,17 +71,6 @@ struct RowGrid {
   const SortedHit* hits;
 };
 
-__device__ __forceinline__ RowGrid row_grid(const Workspace& ws, int R, int s, int r) {
-  const RowHdr h = ws.hdr[(int64_t)s * R + r];
-  RowGrid G;
-  G.ymin = h.ymin; G.zmin = h.zmin; G.iby = h.iby; G.ibz = h.ibz;
-  G.ny = h.ny;
-  G.nz = h.nz;
-  G.bins = ws.bins + 2 * (int64_t)h.bin_half;
-  G.hits = ws.sorted + h.hit_base;
-  return G;
-}
-
 // ------------------------------------------------------------------- reset
 __global__ void k_reset(unsigned long long* c, int n) {
   if ((int)threadIdx.x < n) c[threadIdx.x] = 0ull;
@@ -267,6 +256,7 @@ __device__ __forceinline__ void for_hits(const RowGrid& G, const BinRange& br, F
 }
 
 constexpr int kNfKeep = 8;
+constexpr int kNfMaxRows = 32;  // pad rows per neighbour-finder workgroup, at most
 
 // Score the pair (up j, down k) for the hit (yi, zi) and keep the
 // lexicographic minimum of (chi2, j, k) among pairs within the cut.
@@ -287,6 +277,8 @@ __device__ __forceinline__ void nf_consider(float yi, float zi, float t, float c
 // Grid of row rr of sector s, pointing into the LDS copy when the row is
 // inside the staged range.
 struct Stage {
+  const RowHdr* hdr;      // LDS: headers of rows [r_lo, r_hi]
+  const float4* rowk;     // LDS: rowk of rows [r_lo, r_hi]
   int r_lo, r_hi;         // staged rows [r_lo, r_hi]
   int64_t hit0, bin0;     // global sorted position / bin-table offset of the first staged row
   const SortedHit* hits;  // LDS
@@ -300,7 +292,15 @@ struct Stage {
 // is slower for both.)
 template <bool kLds>
 __device__ __forceinline__ RowGrid staged_grid(const Workspace& ws, int R, int s, int rr, const Stage& S) {
-  RowGrid G = row_grid(ws, R, s, rr);
+  const RowHdr h = S.hdr[rr - S.r_lo];
+  RowGrid G;
+  G.ymin = h.ymin; G.zmin = h.zmin; G.iby = h.iby; G.ibz = h.ibz;
+  G.ny = h.ny;
+  G.nz = h.nz;
+  G.bins = ws.bins + 2 * (int64_t)h.bin_half;
+  G.hits = ws.sorted + h.hit_base;
+  (void)R;
+  (void)s;  // the header comes from the block's LDS copy
   if (kLds) {
     G.hits = S.hits + (G.hits - (ws.sorted + S.hit0));
     G.bins = S.bins + (G.bins - (ws.bins + S.bin0));
@@ -321,7 +321,7 @@ __device__ __forceinline__ void nf_hits(const SortedHit* own, int n, int64_t a, 
       const RowGrid U = staged_grid<kLds>(ws, R, s, r + 1, S);
       const RowGrid D = staged_grid<kLds>(ws, R, s, r - 1, S);
       if (U.ny > 0 && D.ny > 0) {
-        const float4 f = rowk[r];
+        const float4 f = S.rowk[r - S.r_lo];
         const float fu = f.x, fd = f.y, t = f.z;
         const float yi = me.y, zi = me.z;
         const float yu = yi * fu, zu = zi * fu;
@@ -401,6 +401,16 @@ __global__ __launch_bounds__(256) void k_neighbours(Inputs in, Span sp, int R, c
   S.on = false;
   S.r_lo = max(c0 - 1, 0);
   S.r_hi = min(c1, R - 1);
+  // row headers and row constants of the block's rows and their neighbours
+  __shared__ RowHdr nf_hdr[kNfMaxRows + 2];
+  __shared__ float4 nf_rowk[kNfMaxRows + 2];
+  for (int k = threadIdx.x; k <= S.r_hi - S.r_lo; k += blockDim.x) {
+    nf_hdr[k] = ws.hdr[(int64_t)s * R + S.r_lo + k];
+    nf_rowk[k] = rowk[S.r_lo + k];
+  }
+  S.hdr = nf_hdr;
+  S.rowk = nf_rowk;
+  __syncthreads();
   {
     const int64_t h0 = a + rf[S.r_lo], h1 = a + rf[S.r_hi + 1];
     const int64_t b0 = 2 * (h0 + (int64_t)s * R + S.r_lo);
@@ -2076,6 +2086,7 @@ hipError_t launch_grid(const Inputs& in, Span sp, int n_rows, float bin_hits, co
 hipError_t launch_neighbours(const Inputs& in, Span sp, int n_rows, const float4* rowk, const Consts& c,
                              const Workspace& ws, int32_t* up, int32_t* dn, int block, int rows, int lds_bytes,
                              hipStream_t st) {
+  rows = std::max(1, std::min(rows, kNfMaxRows));  // the workgroup stages the headers of rows + 2 rows
   const int64_t chunks = (n_rows + rows - 1) / rows;
   const int64_t items = (int64_t)(sp.s1 - sp.s0) * chunks;
   if (sp.h1 - sp.h0 == 0 || items == 0) return hipSuccess;
