@@ -65,9 +65,10 @@ def profiled_traffic(workload_name, tuning):
 
 DEAD_BAND = (70, 8)  # pad rows without clusters in the merging leg's second batch
 # binary64 operations of the merging's chi^2 pass: one row step of the transport (50 for the state
-# and the Jacobian, 400 for F C F^T over all 5x5 indices), and per pair the summed covariance,
-# Cholesky factorisation, forward substitution and the difference (110)
-MERGE_FLOPS_PER_STEP = 450
+# and the Jacobian, 190 for F C F^T over the structurally nonzero entries of F: 55 + 40 products and
+# as many additions), and per pair the summed covariance, Cholesky factorisation, forward
+# substitution and the difference (110)
+MERGE_FLOPS_PER_STEP = 240
 MERGE_FLOPS_PER_PAIR = 110
 PEAK_FP64_TFLOPS = 78.6
 

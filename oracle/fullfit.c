@@ -90,19 +90,25 @@ static int transport(real* x, real* p, real x1, real kb, real F[5][5]) {
   return 0;
 }
 
-/* C <- F C F^T on the packed lower triangle */
+/* structurally nonzero entries of F: the identity and a, b, e, dS, f, d */
+static int nz(int i, int j) { return i == j || (i == 0 && (j == 2 || j == 4)) || (i == 1 && j >= 2) || (i == 2 && j == 4); }
+
+/* C <- F C F^T on the packed lower triangle; each sum runs over k ascending
+ * and leaves out the terms where F is zero by construction */
 static void transport_cov(real* C, real F[5][5]) {
   real M[5][5];
   for (int i = 0; i < 5; ++i)
     for (int j = 0; j < 5; ++j) {
       real acc = LIT(0.0);
-      for (int k = 0; k < 5; ++k) acc = acc + F[i][k] * C[tri(k, j)];
+      for (int k = 0; k < 5; ++k)
+        if (nz(i, k)) acc = acc + F[i][k] * C[tri(k, j)];
       M[i][j] = acc;
     }
   for (int i = 0; i < 5; ++i)
     for (int j = 0; j <= i; ++j) {
       real acc = LIT(0.0);
-      for (int k = 0; k < 5; ++k) acc = acc + M[i][k] * F[j][k];
+      for (int k = 0; k < 5; ++k)
+        if (nz(j, k)) acc = acc + M[i][k] * F[j][k];
       C[tri(i, j)] = acc;
     }
 }

@@ -1353,6 +1353,15 @@ __device__ __forceinline__ double ff_F(const FitJac& J, int i, int j) {
   return 0.0;
 }
 
+// Structurally nonzero entries of F (the identity and a, b, e, dS, f, d):
+// the covariance products skip the others.  A skipped term would add +-0 to
+// a running sum that starts at +0, which leaves it unchanged for finite
+// covariances, so the order and rounding of the remaining terms are those of
+// the full sum.
+__host__ __device__ constexpr bool ff_nz(int i, int j) {
+  return i == j || (i == 0 && (j == 2 || j == 4)) || (i == 1 && j >= 2) || (i == 2 && j == 4);
+}
+
 // State transport to x1 (the tracklet filter's formulas) and the Jacobian.
 __device__ __forceinline__ int ff_transport(double& x, double* p, double x1, double kb, FitJac* J) {
   const double dx = x1 - x;
@@ -1397,7 +1406,8 @@ __device__ __forceinline__ void ff_transport_cov(double* C, const FitJac& J) {
     for (int j = 0; j < 5; ++j) {
       double acc = 0.0;
 #pragma unroll
-      for (int k = 0; k < 5; ++k) acc = acc + ff_F(J, i, k) * C[ff_tri(k, j)];
+      for (int k = 0; k < 5; ++k)
+        if (ff_nz(i, k)) acc = acc + ff_F(J, i, k) * C[ff_tri(k, j)];
       M[i][j] = acc;
     }
 #pragma unroll
@@ -1406,7 +1416,8 @@ __device__ __forceinline__ void ff_transport_cov(double* C, const FitJac& J) {
     for (int j = 0; j <= i; ++j) {
       double acc = 0.0;
 #pragma unroll
-      for (int k = 0; k < 5; ++k) acc = acc + M[i][k] * ff_F(J, j, k);
+      for (int k = 0; k < 5; ++k)
+        if (ff_nz(j, k)) acc = acc + M[i][k] * ff_F(J, j, k);
       C[ff_tri(i, j)] = acc;
     }
 }
