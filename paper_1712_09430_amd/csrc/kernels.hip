@@ -120,6 +120,8 @@ __device__ __forceinline__ float wave_max(float v) {
   return v;
 }
 
+constexpr int kGridKeep = 4;  // 64-hit rounds of a row kept in registers by the grid build
+
 __global__ __launch_bounds__(64) void k_grid(Inputs in, Span sp, int R, float bin_hits, Workspace ws) {
   __shared__ int cnt[kMaxBinsPerRow];
   const int item = blockIdx.x;
@@ -139,23 +141,42 @@ __global__ __launch_bounds__(64) void k_grid(Inputs in, Span sp, int R, float bi
     }
     return;
   }
+  // the row's first kGridKeep * 64 hits stay in registers across the three
+  // passes (range, count, scatter); the rest are read again
+  float cy[kGridKeep], cz[kGridKeep];
+  int cb[kGridKeep];
   float ylo = FLT_MAX, yhi = -FLT_MAX, zlo = FLT_MAX, zhi = -FLT_MAX;
-  for (int k = lane; k < n; k += 64) {
+#pragma unroll
+  for (int q = 0; q < kGridKeep; ++q) {
+    const int k = lane + 64 * q;
+    cy[q] = 0.0f;
+    cz[q] = 0.0f;
+    if (k < n) {
+      cy[q] = in.y[g + k];
+      cz[q] = in.z[g + k];
+      ylo = fminf(ylo, cy[q]); yhi = fmaxf(yhi, cy[q]);
+      zlo = fminf(zlo, cz[q]); zhi = fmaxf(zhi, cz[q]);
+    }
+  }
+  for (int k = lane + 64 * kGridKeep; k < n; k += 64) {
     const float y = in.y[g + k], z = in.z[g + k];
     ylo = fminf(ylo, y); yhi = fmaxf(yhi, y);
     zlo = fminf(zlo, z); zhi = fmaxf(zhi, z);
   }
   ylo = wave_min(ylo); yhi = wave_max(yhi);
   zlo = wave_min(zlo); zhi = wave_max(zhi);
+  // grid shape: only the searches' speed depends on it (they test windows
+  // exactly and take bin ranges with a margin), so hardware reciprocal and
+  // square root are used here
   const int cap = min(2 * n + 1, kMaxBinsPerRow);
-  int target = (int)fminf(ceilf((float)n / bin_hits), (float)cap);
+  int target = (int)fminf(ceilf((float)n * __builtin_amdgcn_rcpf(bin_hits)), (float)cap);
   target = max(target, 1);
   const float Ly = yhi - ylo, Lz = zhi - zlo;
   int ny = 1, nz = 1;
   if (Ly > 0.0f && Lz > 0.0f) {
-    const float w = sqrtf(Ly * Lz / (float)target);
-    ny = (int)fminf(ceilf(Ly / w), (float)target);
-    nz = (int)fminf(ceilf(Lz / w), (float)target);
+    const float iw = __builtin_amdgcn_rsqf(Ly * Lz * __builtin_amdgcn_rcpf((float)target));
+    ny = (int)fminf(ceilf(Ly * iw), (float)target);
+    nz = (int)fminf(ceilf(Lz * iw), (float)target);
   } else if (Ly > 0.0f) {
     ny = target;
   } else if (Lz > 0.0f) {
@@ -166,8 +187,8 @@ __global__ __launch_bounds__(64) void k_grid(Inputs in, Span sp, int R, float bi
   if (ny * nz > cap) {
     if (ny >= nz) ny = max(1, cap / nz); else nz = max(1, cap / ny);
   }
-  const float iby = Ly > 0.0f ? (float)ny / Ly : 0.0f;
-  const float ibz = Lz > 0.0f ? (float)nz / Lz : 0.0f;
+  const float iby = Ly > 0.0f ? (float)ny * __builtin_amdgcn_rcpf(Ly) : 0.0f;
+  const float ibz = Lz > 0.0f ? (float)nz * __builtin_amdgcn_rcpf(Lz) : 0.0f;
   const float ymin = Ly > 0.0f ? ylo : 0.0f;
   const float zmin = Lz > 0.0f ? zlo : 0.0f;
   const int nb = ny * nz;
@@ -177,7 +198,15 @@ __global__ __launch_bounds__(64) void k_grid(Inputs in, Span sp, int R, float bi
   }
   for (int k = lane; k < nb; k += 64) cnt[k] = 0;
   __syncthreads();
-  for (int k = lane; k < n; k += 64) {
+#pragma unroll
+  for (int q = 0; q < kGridKeep; ++q) {
+    cb[q] = 0;
+    if (lane + 64 * q < n) {
+      cb[q] = bin_of(cz[q], zmin, ibz, nz) * ny + bin_of(cy[q], ymin, iby, ny);
+      atomicAdd(&cnt[cb[q]], 1);
+    }
+  }
+  for (int k = lane + 64 * kGridKeep; k < n; k += 64) {
     const int b = bin_of(in.z[g + k], zmin, ibz, nz) * ny + bin_of(in.y[g + k], ymin, iby, ny);
     atomicAdd(&cnt[b], 1);
   }
@@ -202,7 +231,17 @@ __global__ __launch_bounds__(64) void k_grid(Inputs in, Span sp, int R, float bi
   }
   if (lane == 0) bins[nb] = n;
   __syncthreads();
-  for (int k = lane; k < n; k += 64) {
+#pragma unroll
+  for (int q = 0; q < kGridKeep; ++q) {
+    const int k = lane + 64 * q;
+    if (k < n) {
+      const int pos = atomicAdd(&cnt[cb[q]], 1);
+      SortedHit h;
+      h.y = cy[q]; h.z = cz[q]; h.idx = f0 + k; h.row = r;
+      ws.sorted[g + pos] = h;
+    }
+  }
+  for (int k = lane + 64 * kGridKeep; k < n; k += 64) {
     const float y = in.y[g + k], z = in.z[g + k];
     const int b = bin_of(z, zmin, ibz, nz) * ny + bin_of(y, ymin, iby, ny);
     const int pos = atomicAdd(&cnt[b], 1);
