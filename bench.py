@@ -308,12 +308,16 @@ def serving_leg(args, tuning, log):
     order = rng.integers(0, len(pool), args.serve_events)
     arrival = serve.poisson_arrivals(args.serve_events, args.serve_rate, seed=4)
     src = serve.EventStream(pool, order, arrival, pool[0].row_x)
-    res = serve.serve(src, tuning=tuning, warmup_events=args.serve_warmup)
+    from paper_1712_09430_amd import autotune
+    stun = autotune.cached_serve_tuning() if args.tuning == "auto" else None
+    source = "autotuner serving result" if stun else "the batch tuning"
+    stun = stun or tuning
+    res = serve.serve(src, tuning=stun, warmup_events=args.serve_warmup)
     log(f"[bench] serving: p50 {res['p50_ms']:.3f} ms, p99 {res['p99_ms']:.3f} ms, {res['hits_per_s']:.4g} hits/s, "
         f"{res['batches']} batches, {res['slots']} slots")
     # the same stream with every event waiting from the start: the server's
     # saturated throughput (H2D, hot path and D2H of overlapping batches)
-    sat = serve.serve(src, tuning=tuning, warmup_events=0, realtime=False)
+    sat = serve.serve(src, tuning=stun, warmup_events=0, realtime=False)
     log(f"[bench] serving saturated: {sat['hits_per_s']:.4g} hits/s, {sat['batches']} batches")
     return {"p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"], "hits_per_s": res["hits_per_s"],
             "events": res["n_events"], "warmup_events": args.serve_warmup, "rate_hz": args.serve_rate,
@@ -323,7 +327,8 @@ def serving_leg(args, tuning, log):
             "latency": "arrival to results in host memory (H2D + hot path + D2H)",
             "saturated_hits_per_s": sat["hits_per_s"], "saturated_batches": sat["batches"],
             "late_fetches": res["late_fetches"],
-            "mean_event_hits": float(src.ev_hits.mean())}
+            "mean_event_hits": float(src.ev_hits.mean()),
+            "tuning_source": source, "tuning_changes": {k: v for k, v in stun.items() if tuning.get(k) != v}}
 
 
 def main():
