@@ -29,6 +29,11 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 # Algorithmic work per unit (binary32 operations of the formulas, division and square root count 1):
 NF_BYTES_PER_HIT = 16.0        # y, z in (8 B) + up, down link out (8 B)
+# the other per-hit stages, algorithmic bytes per hit:
+GRID_BYTES_PER_HIT = 32.0      # y, z in (8 B); grid-sorted record (16 B) and two bin-table entries (8 B) out
+CLEAN_BYTES_PER_HIT = 48.0     # links (8 B), the partners' back links (8 B), y, z (8 B) in; cleaned links (8 B)
+                               # and the chain record (16 B) out
+ROWIDX_BYTES_PER_HIT = 4.0     # row in
 FLOPS_PER_TRANSPORT = 75.0     # binary32 operations of one helix transport incl. covariance
 FLOPS_PER_UPDATE = 39.0        # two scalar Kalman updates
 FLOPS_PER_SEARCH = 6.0         # the two gate widths
@@ -514,8 +519,17 @@ def main():
              "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None, "launch_ms": nf_ms,
              "algorithmic_bytes": nf_bytes}
     rl_nf["frac"] = rl_nf["achieved"] / rl_nf["peak"]
+    others = {}
+    for kern, stage, per_hit in (("k_grid", "grid", GRID_BYTES_PER_HIT), ("k_clean_start", "clean_start",
+                                                                          CLEAN_BYTES_PER_HIT),
+                                 ("k_row_index", "row_index", ROWIDX_BYTES_PER_HIT)):
+        ms_k = stages[stage]
+        byts = per_hit * hits.n_hits
+        others[kern] = {"kernel": kern, "bound": "hbm", "achieved": byts / (ms_k * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "traffic": None, "launch_ms": ms_k, "algorithmic_bytes": byts}
+        others[kern]["frac"] = others[kern]["achieved"] / HBM_PEAK_GBS
     traffic = profiled_traffic(args.workload, tuning)
-    for rl in (rl_tc, rl_nf):
+    for rl in (rl_tc, rl_nf, *others.values()):
         t = traffic.get(rl["kernel"])
         if t:
             rl["traffic"] = t["fetch_bytes"] + t["write_bytes"]
@@ -594,7 +608,7 @@ def main():
                       "tuning": tuning, "tuning_source": tuning_src},
            "plain": plain, "batched_over_plain": (value / plain["hits_per_s"]) if plain else None,
            "serving": serving, "stages_ms": stages, "roofline": {k: v for k, v in dominant.items() if k != "kernel"} |
-           {"kernel": dominant["kernel"]}, "rooflines": {"k_tracklets": rl_tc, "k_neighbours": rl_nf},
+           {"kernel": dominant["kernel"]}, "rooflines": {"k_tracklets": rl_tc, "k_neighbours": rl_nf, **others},
            "selection": sel, "refit": refit, "merge": merge, "scheduling": scheduling, "achievable_peaks": peaks, "precision": precision, "linearity": linearity, "cpu_baseline": cpu}
     print(json.dumps(res), flush=True)
 
