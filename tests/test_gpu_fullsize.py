@@ -92,10 +92,12 @@ def test_batch64_sampled_sectors_bit_exact_and_global_properties():
     assert np.array_equal((rh >= 0).sum(1), trk["n_hits"])
 
 
-def test_batch64_merge_sampled_sectors_bit_exact():
+def test_batch64_refit_and_merge_sampled_sectors_bit_exact():
     """Selection, refit and segment merging after the bench configuration's
-    track call on the 64-event batch: sampled sectors against the oracle."""
+    track call on the 64-event batch: the fits and the links of sampled
+    sectors against the oracle."""
     from _harness import chains, oracle_merge_sector, oracle_params
+    from test_gpu_refit import compare_sector_fits
     b = synth.batch_workload(seed=1, n_events=64)
     tr, hits, out, n, p = run_bench_config(b)
     tracks = tr.tracks_output(hits, out)
@@ -106,13 +108,16 @@ def test_batch64_merge_sampled_sectors_bit_exact():
     merges = tr.merges_output(tracks)
     tr.merge(hits, out, tracks, fits, merges)
     torch.cuda.synchronize()
-    g, m = tracks.numpy(nt, nh), merges.numpy(nt)
+    g, m, f = tracks.numpy(nt, nh), merges.numpy(nt), fits.numpy(nt)
     sizes = np.diff(b.hit_offset)
     rng = np.random.default_rng(77)
     sample = sorted(set(np.argsort(sizes)[-2:].tolist()) | set(rng.choice(b.n_sectors, 8, replace=False).tolist()))
     P = oracle_params(p)
 
     def one(s):
+        bad_fit, _ = compare_sector_fits(b, s, g, f, p)
+        if bad_fit:
+            return bad_fit[:3]
         nxt, chi2, _ = oracle_merge_sector(b, s, P)
         k0, k1 = int(g["track_offset"][s]), int(g["track_offset"][s + 1])
         if k1 - k0 != len(nxt):
