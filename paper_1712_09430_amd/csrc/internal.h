@@ -61,10 +61,11 @@ struct Workspace {
   int64_t* grp_off;      // [H/256/1024 + 8] first slot of each group of 1024 blocks
   int32_t* start_glob;   // [H] global hit index of each tracklet slot
   ChainHit* chain;       // [H] coordinates + cleaned up-link per hit (input order)
-  unsigned* owner;               // [H] tracklet selection: weight of the tracklet that keeps each hit
+  unsigned* owner;               // [H] tracklet selection: weight of the tracklet that keeps each hit (row chunks too dense for LDS)
   int32_t* sel_cnt;              // [H/3 + 2] hits a selected tracklet keeps, or -1
   int2* sel_loc;                 // [H/3 + 2] track and hit offsets within the slot's group of 1024
   longlong2* sel_grp;            // [(H/3)/1024 + 8] group offsets
+  uint16_t* sel_mask;            // [(H/3 + 2) * sel_chunks(R)] kept rows of each valid tracklet, per row chunk
   float4* mrec;                  // [H/3 + 2] segment merging: start x, y, z of each track's tracklet, rows
   unsigned long long* mkey_a;    // [H/3 + 2] segment merging: best continuation as (chi^2 bits, track)
   unsigned long long* mkey_b;    // [H/3 + 2] segment merging: best predecessor as (chi^2 bits, track)
@@ -151,6 +152,10 @@ struct TrackletOut {
 
 // Row stride of the hit-per-row output (whole chunks of 8 rows).
 __host__ __device__ inline int row_stride(int R) { return (R + 7) & ~7; }
+// The selection works on chunks of 16 rows; a tracklet's kept rows are one
+// 16-bit mask per chunk.
+constexpr int kSelRows = 16;
+__host__ __device__ inline int sel_chunks(int R) { return (R + kSelRows - 1) / kSelRows; }
 
 constexpr int kMaxRows = 4096;       // pad rows per sector (row indices are wave-reduced as 16-bit values)
 constexpr int kHitsPerBlock = 256;  // per-hit kernels: block size of clean/start/compaction

@@ -1107,10 +1107,10 @@ __device__ __forceinline__ int64_t sel_slots(const int64_t* toff, int S, int64_t
 }
 
 
-// The selection kernels give each tracklet 16 lanes (4 tracklets per wave):
-// lane l of a group reads the 16-byte pieces l, l+16, l+32 of the record, so
-// the record is read with coalesced loads and the per-hit work of a tracklet
-// is spread over its lanes.  Persistent grid-stride loop over the slots.
+// The emit kernel gives each tracklet 16 lanes (4 tracklets per wave): lane l
+// of a group reads the 16-byte pieces l, l+16, l+32 of the record, so the
+// record is read with coalesced loads and the per-hit work of a tracklet is
+// spread over its lanes.  Persistent grid-stride loop over the slots.
 constexpr int kSelLanes = 16;
 
 struct SelTrk {
@@ -1142,10 +1142,11 @@ __device__ __forceinline__ SelTrk sel_trk(const Inputs& in, int S, const int64_t
 // Claim: one workgroup per (sector, chunk of kSelRows rows).  The owner
 // words of the chunk's hits (contiguous, the hits being sorted by row) are
 // kept in LDS while every valid tracklet of the sector takes the atomic
-// maximum of its weight on its hits in these rows, then written out whole
-// (which also clears the words of hits nobody lists).  A chunk with more hits
-// than the LDS holds works on the owner words in memory instead.
-constexpr int kSelRows = 16;
+// maximum of its weight on its hits in these rows; then each valid tracklet
+// reads back which of its hits in these rows it owns and writes them as the
+// chunk's 16-bit kept-row mask.  A chunk with more hits than the LDS holds
+// works on the owner words in memory instead.
+static_assert(kSelRows == 16, "one 16-bit kept-row mask per chunk");
 
 // Clears the selection's error bits before a selection.
 __global__ void k_sel_flags(Workspace ws) {
@@ -1157,7 +1158,7 @@ constexpr int kSelLdsWords = 8192;
 __global__ __launch_bounds__(256) void k_sel_claim(Inputs in, int S, const int64_t* toff, int64_t slots, int R,
                                                    TrackletOut trk, Workspace ws) {
   __shared__ unsigned own[kSelLdsWords];
-  const int nch = (R + kSelRows - 1) / kSelRows;
+  const int nch = sel_chunks(R);
   const int s = (int)(blockIdx.x / nch);
   const int r0 = (int)(blockIdx.x % nch) * kSelRows;
   const int r1 = min(R, r0 + kSelRows);
@@ -1199,38 +1200,50 @@ __global__ __launch_bounds__(256) void k_sel_claim(Inputs in, int S, const int64
   }
   if (bad) atomicOr(&ws.counters[kCtrError], 4ull);
   if (many) atomicOr(&ws.counters[kCtrError], 16ull);
-  if (lds) {
-    __syncthreads();
-    for (int k = threadIdx.x; k < nh; k += blockDim.x) gown[k] = own[k];
-  }
-}
-
-// Count: 16 lanes per tracklet, the hits whose owner is this tracklet.
-__global__ __launch_bounds__(256) void k_sel_count(Inputs in, int S, const int64_t* toff, int64_t slots, int R,
-                                                   TrackletOut trk, Consts c, Workspace ws) {
-  const int64_t n = sel_slots(toff, S, slots);
-  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int lbits = sel_index_bits(R);
-  const int sub = threadIdx.x & (kSelLanes - 1);
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x / kSelLanes;
-  const int RS4 = row_stride(R) / 4;
-  for (int64_t slot = gtid / kSelLanes; slot < n; slot += stride) {
-    const SelTrk t = sel_trk(in, S, toff, trk, slot, n, lbits);
-    int cnt = 0;
-    if (t.on && t.local < (1 << lbits)) {
-      const int4* rec = reinterpret_cast<const int4*>(trk.row_hit + slot * row_stride(R));
-      for (int q = sub; q < RS4; q += kSelLanes) {
+  if (!lds) __threadfence();
+  __syncthreads();
+  // The owner words are final: the kept rows of each valid tracklet here.
+  const int ch = r0 / kSelRows;
+  for (int64_t slot = t0 + threadIdx.x; slot < t1; slot += blockDim.x) {
+    if (!(trk.flags[slot] & 1)) continue;
+    const int32_t local = (int32_t)(slot - toff[s]);
+    unsigned bits = 0u;
+    if (local < (1 << lbits)) {  // past the index limit a tracklet owns nothing
+      const unsigned key = sel_weight(trk.n_hits[slot], local, lbits);
+      const int4* rec = reinterpret_cast<const int4*>(trk.row_hit + slot * RS + r0);
+      for (int q = 0; q < (r1 - r0 + 3) / 4; ++q) {
         const int4 v = rec[q];
         const int32_t hv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-          const int32_t h = hv[m];
-          if (h >= 0 && h < t.ns) cnt += ws.owner[t.a + h] == t.key;
+          if (hv[m] < 0 || 4 * q + m >= r1 - r0) continue;
+          const int32_t hl = hv[m] - h_lo;
+          if (hl < 0 || hl >= nh) continue;  // reported by the first pass
+          // in memory the words were set by atomics at the device level: read them there
+          const unsigned o = lds ? own[hl] : __hip_atomic_load(&gown[hl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (o == key) bits |= 1u << (4 * q + m);
         }
       }
     }
-    for (int o = kSelLanes / 2; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, kSelLanes);
-    if (sub == 0) ws.sel_cnt[slot] = (t.on && cnt >= c.min_hits) ? cnt : -1;
+    ws.sel_mask[slot * nch + ch] = (uint16_t)bits;
+  }
+}
+
+// Count: one lane per slot, the kept rows of a valid tracklet from its
+// per-chunk masks.
+__global__ __launch_bounds__(256) void k_sel_count(const int64_t* toff, int S, int64_t slots, int R,
+                                                   TrackletOut trk, Consts c, Workspace ws) {
+  const int64_t n = sel_slots(toff, S, slots);
+  const int nch = sel_chunks(R);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; slot < n; slot += stride) {
+    int cnt = -1;
+    if (trk.flags[slot] & 1) {
+      cnt = 0;
+      for (int k = 0; k < nch; ++k) cnt += __popc((unsigned)ws.sel_mask[slot * nch + k]);
+      if (cnt < c.min_hits) cnt = -1;
+    }
+    ws.sel_cnt[slot] = cnt;
   }
 }
 
@@ -1320,6 +1333,7 @@ __global__ __launch_bounds__(256) void k_sel_emit(Inputs in, int S, const int64_
   const int sub = threadIdx.x & (kSelLanes - 1);
   const int64_t stride = nthreads / kSelLanes;
   const int RS4 = row_stride(R) / 4;
+  const int nch = sel_chunks(R);
   for (int64_t slot = gtid / kSelLanes; slot < n; slot += stride) {
     const int cnt = ws.sel_cnt[slot];
     if (cnt < 0) continue;  // the 16 lanes of a slot take this branch together
@@ -1340,9 +1354,11 @@ __global__ __launch_bounds__(256) void k_sel_emit(Inputs in, int S, const int64_
       if (q < RS4) {
         const int4 v = rec[q];
         w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+        // rows 4q..4q+3 of the claim's kept-row mask (chunk q / 4; 4q < row_stride(R) <= 16 * nch)
+        const unsigned bits = (unsigned)ws.sel_mask[slot * nch + (q >> 2)] >> (4 * (q & 3));
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-          own[m] = w[m] >= 0 && w[m] < t.ns && ws.owner[t.a + w[m]] == t.key;
+          own[m] = ((bits >> m) & 1u) != 0u;
           mine += own[m];
         }
       }
@@ -1374,7 +1390,8 @@ __global__ __launch_bounds__(256) void k_sel_emit(Inputs in, int S, const int64_
 // result at the outermost hit.  One lane per track, in binary64 (MI355X runs
 // binary64 vector arithmetic at the binary32 rate; in binary32 the long
 // coupled covariance products lose about 1e-3 cm in z and 1e-3 in q/pT).
-// The matrix products run over every index (zeros included) in a fixed order.
+// The matrix products run, in a fixed order, over the entries of F that are
+// not zero by construction.
 __device__ __forceinline__ int ff_tri(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
 
 struct FitJac {
@@ -2204,11 +2221,11 @@ hipError_t launch_select(const Inputs& in, int S, const int64_t* toff, int64_t c
   const int64_t ng = slots / kScanGroup + 1;  // covers entries [0, slots]
   (void)n_hits;
   hipLaunchKernelGGL(k_sel_flags, dim3(1), dim3(64), 0, st, ws);
-  const int64_t claim_blocks = (int64_t)S * ((n_rows + kSelRows - 1) / kSelRows);
+  const int64_t claim_blocks = (int64_t)S * sel_chunks(n_rows);
   if (claim_blocks > 0)
     hipLaunchKernelGGL(k_sel_claim, dim3((unsigned)claim_blocks), dim3(256), 0, st, in, S, toff, slots, n_rows, trk,
                        ws);
-  hipLaunchKernelGGL(k_sel_count, dim3(grid), dim3(256), 0, st, in, S, toff, slots, n_rows, trk, c, ws);
+  hipLaunchKernelGGL(k_sel_count, dim3(grid), dim3(256), 0, st, toff, S, slots, n_rows, trk, c, ws);
   hipLaunchKernelGGL(k_sel_scan_local, dim3((unsigned)ng), dim3(kScanGroup), 0, st, toff, S, slots, ws);
   hipLaunchKernelGGL(k_sel_scan_top, dim3(1), dim3(1024), 0, st, ng, ws);
   hipLaunchKernelGGL(k_sel_emit, dim3(grid), dim3(256), 0, st, in, S, toff, slots, n_rows, trk, ws, out);

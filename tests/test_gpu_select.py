@@ -60,6 +60,22 @@ def test_one_sector_matches_oracle(seed):
     check_all(b, g, C.catpc_default_params(), [0])
 
 
+def test_dense_row_chunks_claim_in_memory():
+    """A sector dense enough that most chunks of 16 rows hold more hits than
+    the claim keeps in LDS (8192): those chunks claim on the owner words in
+    memory, the last one in LDS; the selection still equals the oracle's."""
+    from paper_1712_09430_amd import catpc as C
+    b = synth.sector_workload(seed=5, n_tracks=900)
+    per_row = np.bincount(b.row, minlength=len(b.row_x))
+    chunks = [int(per_row[r:r + 16].sum()) for r in range(0, len(b.row_x), 16)]
+    assert max(chunks) > 8192 and min(chunks) <= 8192
+    tr, hits, out, st, n = run_gpu(b)
+    assert st == C.CATPC_OK
+    _, g, nt, nh = select_gpu(tr, hits, out)
+    assert nt > 300
+    check_all(b, g, C.catpc_default_params(), [0])
+
+
 def test_uneven_batch_graph_and_plain_launches_agree():
     from paper_1712_09430_amd import catpc as C
     b = synth.batch_workload(seed=7, n_events=3, lo=20, hi=3000)
