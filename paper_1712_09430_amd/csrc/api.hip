@@ -37,7 +37,7 @@ catpc_status hip_fail(hipError_t e, const char* what) {
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t row_first, hdr, bins, sorted, raw_up, raw_dn, mask, blk_cnt, blk_off, grp_off, start_glob, chain,
+  size_t row_first, hdr, bins, sorted, raw_up, raw_dn, mask, blk_sec, blk_cnt, blk_off, grp_off, start_glob, chain,
       owner, sel_cnt, sel_loc, sel_grp, sel_mask, mrec, mkey_a, mkey_b, mpair, mover, mslot, mchunk, counters;
   size_t total;
 };
@@ -54,6 +54,7 @@ Layout plan(int32_t R, int64_t H, int32_t S) {
   L.raw_up = take(sizeof(int32_t) * (size_t)(H + 1));
   L.raw_dn = take(sizeof(int32_t) * (size_t)(H + 1));
   L.mask = take(sizeof(uint64_t) * (nblk * (kHitsPerBlock / 64) + 8));
+  L.blk_sec = take(sizeof(int32_t) * (nblk + 8));
   L.blk_cnt = take(sizeof(int32_t) * (nblk + 8));
   L.blk_off = take(sizeof(int64_t) * (nblk + 8));
   L.grp_off = take(sizeof(int64_t) * (nblk / 1024 + 8));
@@ -448,6 +449,7 @@ catpc_status catpc_create(int32_t n_rows, const float* row_x, const catpc_params
       w.raw_up = (int32_t*)(b + L.raw_up);
       w.raw_dn = (int32_t*)(b + L.raw_dn);
       w.start_mask = (uint64_t*)(b + L.mask);
+      w.blk_sec = (int32_t*)(b + L.blk_sec);
       w.blk_cnt = (int32_t*)(b + L.blk_cnt);
       w.blk_off = (int64_t*)(b + L.blk_off);
       w.grp_off = (int64_t*)(b + L.grp_off);

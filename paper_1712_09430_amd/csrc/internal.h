@@ -56,6 +56,7 @@ struct Workspace {
   int32_t* raw_up;       // [H] neighbour-finder links when the caller does not keep them
   int32_t* raw_dn;       // [H]
   uint64_t* start_mask;  // [H/64 + 8] start-hit bits per wave
+  int32_t* blk_sec;      // [H/256 + 8] sector of the first hit of each block of kHitsPerBlock hits of the span
   int32_t* blk_cnt;      // [H/256 + 8] start hits per block
   int64_t* blk_off;      // [H/256 + 8] first slot of each block, relative to its group of 1024 blocks
   int64_t* grp_off;      // [H/256/1024 + 8] first slot of each group of 1024 blocks

@@ -45,6 +45,12 @@ __device__ __forceinline__ int sector_of(const int64_t* off, int s0, int s1, int
   return lo;
 }
 
+// Sector of hit i, walking forward from sector s (off[s] <= i, s < s1).
+__device__ __forceinline__ int sector_from(const int64_t* off, int s1, int s, int64_t i) {
+  while (s + 1 < s1 && off[s + 1] <= i) ++s;
+  return s;
+}
+
 // Bin of a coordinate: monotone non-decreasing in v, clamped to [0, n-1].
 __device__ __forceinline__ int bin_of(float v, float vmin, float inv, int n) {
   float f = (v - vmin) * inv;
@@ -80,16 +86,23 @@ __global__ void k_reset(unsigned long long* c, int n) {
 // Blocks [0, item_blocks): one thread per (sector, row 0..R) item, first hit
 // of the row by binary search (monotone in r for any input; row 0 starts at
 // the sector's first hit and row R at its end, so the rows always partition
-// the sector).  Remaining blocks: one thread per hit, order and range check.
+// the sector); the items of a sector also record it as the sector of the
+// kHitsPerBlock-hit blocks that start in it, for the per-hit kernels after the
+// neighbour search.  Remaining blocks: one thread per hit, order and range
+// check.
 __global__ __launch_bounds__(256) void k_row_index(Inputs in, Span sp, int R, const float* __restrict__ row_x,
-                                                   int32_t* row_first, unsigned long long* counters,
-                                                   int64_t n_items, int64_t item_blocks) {
+                                                   int32_t* row_first, int32_t* blk_sec,
+                                                   unsigned long long* counters, int64_t n_items,
+                                                   int64_t item_blocks) {
   if ((int64_t)blockIdx.x < item_blocks) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_items) return;
     const int s = sp.s0 + (int)(g / (R + 1));
     const int r = (int)(g % (R + 1));
     const int64_t a = in.hit_offset[s], b = in.hit_offset[s + 1];
+    // blocks whose first hit sp.h0 + k * kHitsPerBlock lies in [a, b)
+    const int64_t k0 = (a - sp.h0 + kHitsPerBlock - 1) / kHitsPerBlock, k1 = (b - sp.h0 + kHitsPerBlock - 1) / kHitsPerBlock;
+    for (int64_t k = k0 + r; k < k1; k += R + 1) blk_sec[k] = s;
     int64_t lo = a, hi = b;
     while (lo < hi) {
       const int64_t mid = (lo + hi) >> 1;
@@ -479,9 +492,8 @@ __global__ __launch_bounds__(kHitsPerBlock) void k_clean_start(Inputs in, Span s
                                                                const int32_t* __restrict__ dn,
                                                                int32_t* __restrict__ uc_out,
                                                                int32_t* __restrict__ dc_out, Workspace ws) {
-  const int64_t first = sp.h0 + (int64_t)blockIdx.x * kHitsPerBlock;
-  const int64_t i = first + threadIdx.x;
-  const int s = block_sector(in.hit_offset, sp.s0, sp.s1, first, min(i, sp.h1 - 1));
+  const int64_t i = sp.h0 + (int64_t)blockIdx.x * kHitsPerBlock + threadIdx.x;
+  const int s = sector_from(in.hit_offset, sp.s1, ws.blk_sec[blockIdx.x], min(i, sp.h1 - 1));
   bool start = false;
   if (i < sp.h1) {
     const int64_t a = in.hit_offset[s];
@@ -586,24 +598,34 @@ __device__ __forceinline__ int64_t block_slot(const Workspace& ws, int64_t b) {
 }
 
 // ----------------------------------------------------------------- compact
-__global__ __launch_bounds__(kHitsPerBlock) void k_compact(Inputs in, Span sp, int64_t nblk, int64_t* toff,
-                                                           int32_t* __restrict__ start_hit, Workspace ws) {
-  constexpr int W = kHitsPerBlock / 64;
-  if ((int64_t)blockIdx.x < nblk) {
-    const int64_t first = sp.h0 + (int64_t)blockIdx.x * kHitsPerBlock;
-    const int64_t i = first + threadIdx.x;
-    const int s = block_sector(in.hit_offset, sp.s0, sp.s1, first, min(i, sp.h1 - 1));
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const unsigned long long m = ws.start_mask[(int64_t)blockIdx.x * W + wave];
-    if (i < sp.h1 && ((m >> lane) & 1ull)) {
-      int64_t pos = block_slot(ws, blockIdx.x);
-      for (int w = 0; w < wave; ++w) pos += __popcll(ws.start_mask[(int64_t)blockIdx.x * W + w]);
-      pos += __popcll(m & ((1ull << lane) - 1ull));
-      start_hit[pos] = (int32_t)(i - in.hit_offset[s]);
-      ws.start_glob[pos] = (int32_t)i;
+// Blocks [0, word_blocks): one thread per 64-hit word of the start mask; a
+// word with start hits writes them in ascending order from its offset (the
+// block offset plus the counts of the words before it in the block).  The
+// remaining blocks: one thread per sector boundary, the sector's first slot.
+__global__ __launch_bounds__(kHitsPerBlock) void k_compact(Inputs in, Span sp, int64_t nblk, int64_t word_blocks,
+                                                           int64_t* toff, int32_t* __restrict__ start_hit,
+                                                           Workspace ws) {
+  constexpr int W = kHitsPerBlock / 64;  // mask words per clean/start block
+  if ((int64_t)blockIdx.x < word_blocks) {
+    const int64_t g = (int64_t)blockIdx.x * kHitsPerBlock + threadIdx.x;  // mask word
+    const int64_t i0 = sp.h0 + g * 64;
+    unsigned long long m = g < nblk * W ? ws.start_mask[g] : 0ull;  // no bits past the span's last hit
+    if (m) {
+      const int64_t b = g / W;
+      int s = ws.blk_sec[b];
+      int64_t pos = block_slot(ws, b);
+      for (int64_t w = b * W; w < g; ++w) pos += __popcll(ws.start_mask[w]);
+      do {
+        const int64_t i = i0 + (__ffsll((long long)m) - 1);
+        while (s + 1 < sp.s1 && in.hit_offset[s + 1] <= i) ++s;
+        start_hit[pos] = (int32_t)(i - in.hit_offset[s]);
+        ws.start_glob[pos] = (int32_t)i;
+        ++pos;
+        m &= m - 1ull;
+      } while (m);
     }
   } else {
-    const int s = sp.s0 + 1 + (int)(((int64_t)blockIdx.x - nblk) * kHitsPerBlock + threadIdx.x);
+    const int s = sp.s0 + 1 + (int)(((int64_t)blockIdx.x - word_blocks) * kHitsPerBlock + threadIdx.x);
     if (s <= sp.s1) {
       const int64_t j = in.hit_offset[s] - sp.h0;
       const int64_t b = j / kHitsPerBlock;
@@ -1515,6 +1537,11 @@ __device__ __forceinline__ int ff_update(double* p, double* C, double my, double
 __global__ __launch_bounds__(256) void k_fullfit(Inputs in, int S, int R, const float* __restrict__ row_x,
                                                  Consts c, const int64_t* toff, TrackletOut trk, int64_t trk_cap,
                                                  TracksOut tr, FitsOut out, Workspace ws) {
+  // the row positions in LDS (R floats of dynamic LDS): read at every row step
+  extern __shared__ __align__(16) unsigned char ff_dyn[];
+  float* rxs = reinterpret_cast<float*>(ff_dyn);
+  for (int r = threadIdx.x; r < R; r += blockDim.x) rxs[r] = row_x[r];
+  __syncthreads();
   const int64_t n = min(tr.track_offset[S], min(tr.track_capacity, out.capacity));
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
@@ -1544,8 +1571,19 @@ __global__ __launch_bounds__(256) void k_fullfit(Inputs in, int S, int R, const 
       x = (double)trk.x_ref[slot];
 #pragma unroll
       for (int i = 0; i < 5; ++i) p[i] = (double)trk.param[5 * slot + i];
+      // The hit data are read ahead: when hit k is used, the row, y and z of
+      // hit k+1 and the index of hit k+2 are already on their way.
+      const float* yv = in.y + a;
+      const float* zv = in.z + a;
+      const int32_t* rv = in.row + a;
+      const int32_t* hv = tr.track_hits + h0;
+      float yk = yv[h_first], zk = zv[h_first];
+      int32_t h1 = nh > 1 ? hv[1] : -1, h2 = nh > 2 ? hv[2] : -1;
+      int r1 = 0;
+      float y1 = 0.f, z1 = 0.f;
+      if (h1 >= 0 && h1 < ns) { r1 = rv[h1]; y1 = yv[h1]; z1 = zv[h1]; }
       for (int r = start_row + 1; r <= r_first && !fl; ++r)
-        fl = ff_transport(x, p, (double)row_x[r], c.kbd, nullptr);
+        fl = ff_transport(x, p, (double)rxs[r], c.kbd, nullptr);
       if (!fl) {
         C[ff_tri(0, 0)] = c.sy2d;
         C[ff_tri(1, 1)] = c.sz2d;
@@ -1553,24 +1591,27 @@ __global__ __launch_bounds__(256) void k_fullfit(Inputs in, int S, int R, const 
         C[ff_tri(3, 3)] = 1.0;
         C[ff_tri(4, 4)] = 100.0;
         int k = 0;
-        int32_t hk = h_first;
         int rk = r_first;
         for (int r = r_first; r <= r_last; ++r) {
           if (r > r_first) {
             FitJac J;
-            fl = ff_transport(x, p, (double)row_x[r], c.kbd, &J);
+            fl = ff_transport(x, p, (double)rxs[r], c.kbd, &J);
             if (fl) break;
             ff_transport_cov(C, J);
           }
           if (k < nh && rk == r) {
-            fl = ff_update(p, C, (double)in.y[a + hk], (double)in.z[a + hk], c.sy2d, c.sz2d, chi2);
+            fl = ff_update(p, C, (double)yk, (double)zk, c.sy2d, c.sz2d, chi2);
             if (fl) break;
             ++k;
             ++used;
             if (k < nh) {
-              hk = tr.track_hits[h0 + k];
-              if (hk < 0 || hk >= ns) { fl = 64; break; }
-              rk = in.row[a + hk];
+              if (h1 < 0 || h1 >= ns) { fl = 64; break; }  // hit k
+              rk = r1;
+              yk = y1;
+              zk = z1;
+              h1 = h2;  // hit k+1
+              if (k + 1 < nh && h1 >= 0 && h1 < ns) { r1 = rv[h1]; y1 = yv[h1]; z1 = zv[h1]; }
+              if (k + 2 < nh) h2 = hv[k + 2];
             }
           }
         }
@@ -2139,7 +2180,7 @@ hipError_t launch_row_index(const Inputs& in, Span sp, int n_rows, const float* 
   const int64_t total = item_blocks + blocks_for(sp.h1 - sp.h0, block);
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_row_index, dim3((unsigned)total), dim3(block), 0, st, in, sp, n_rows, row_x, ws.row_first,
-                     ws.counters, n_items, item_blocks);
+                     ws.blk_sec, ws.counters, n_items, item_blocks);
   return hipGetLastError();
 }
 
@@ -2182,10 +2223,12 @@ hipError_t launch_scan(Span sp, int64_t* toff, const Workspace& ws, hipStream_t 
 hipError_t launch_compact(const Inputs& in, Span sp, int64_t* toff, int32_t* start_hit, const Workspace& ws,
                           hipStream_t st) {
   const int64_t nblk = (sp.h1 - sp.h0 + kHitsPerBlock - 1) / kHitsPerBlock;
+  const int64_t word_blocks = blocks_for(nblk * (kHitsPerBlock / 64), kHitsPerBlock);
   const int64_t nsec_blk = ((int64_t)(sp.s1 - sp.s0) + kHitsPerBlock - 1) / kHitsPerBlock;
-  const int64_t grid = nblk + nsec_blk;
+  const int64_t grid = word_blocks + nsec_blk;
   if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_compact, dim3((unsigned)grid), dim3(kHitsPerBlock), 0, st, in, sp, nblk, toff, start_hit, ws);
+  hipLaunchKernelGGL(k_compact, dim3((unsigned)grid), dim3(kHitsPerBlock), 0, st, in, sp, nblk, word_blocks, toff,
+                     start_hit, ws);
   return hipGetLastError();
 }
 
@@ -2235,8 +2278,8 @@ hipError_t launch_select(const Inputs& in, int S, const int64_t* toff, int64_t c
 hipError_t launch_fullfit(const Inputs& in, int S, int n_rows, const float* row_x, const Consts& c,
                           const int64_t* toff, const TrackletOut& trk, int64_t trk_cap, const TracksOut& tr,
                           const FitsOut& out, const Workspace& ws, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_fullfit, dim3(grid), dim3(256), 0, st, in, S, n_rows, row_x, c, toff, trk, trk_cap, tr, out,
-                     ws);
+  hipLaunchKernelGGL(k_fullfit, dim3(grid), dim3(256), sizeof(float) * (size_t)n_rows, st, in, S, n_rows, row_x, c,
+                     toff, trk, trk_cap, tr, out, ws);
   return hipGetLastError();
 }
 
