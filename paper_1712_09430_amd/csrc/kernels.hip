@@ -58,18 +58,6 @@ __device__ __forceinline__ int bin_of(float v, float vmin, float inv, int n) {
   return (int)f;
 }
 
-// Sector of hit i, for the threads of a block whose hits start at `first`
-// (first <= i): one binary search per block, broadcast through LDS, then a
-// short forward walk.  Every thread of the block must call it.
-__device__ __forceinline__ int block_sector(const int64_t* off, int s0, int s1, int64_t first, int64_t i) {
-  __shared__ int s_first;
-  if (threadIdx.x == 0) s_first = sector_of(off, s0, s1, first);
-  __syncthreads();
-  int s = s_first;
-  while (s + 1 < s1 && off[s + 1] <= i) ++s;
-  return s;
-}
-
 struct RowGrid {
   float ymin, zmin, iby, ibz;
   int ny, nz;
@@ -110,13 +98,15 @@ __global__ __launch_bounds__(256) void k_row_index(Inputs in, Span sp, int R, co
     }
     row_first[(int64_t)s * (R + 1) + r] = (int32_t)((r == R ? b : r == 0 ? a : lo) - a);
   } else {
-    const int64_t first = sp.h0 + ((int64_t)blockIdx.x - item_blocks) * blockDim.x;
-    const int64_t i = first + threadIdx.x;
-    const int s = block_sector(in.hit_offset, sp.s0, sp.s1, first, min(i, sp.h1 - 1));
+    const int64_t i = sp.h0 + ((int64_t)blockIdx.x - item_blocks) * blockDim.x + threadIdx.x;
     if (i < sp.h1) {
       const int32_t r = in.row[i];
       bool ok = r >= 0 && r < R;
-      if (i > in.hit_offset[s]) ok = ok && in.row[i - 1] <= r;
+      if (ok && i > sp.h0 && in.row[i - 1] > r) {
+        // rows may fall only where a sector starts (rare: look the sector up then)
+        const int s = sector_of(in.hit_offset, sp.s0, sp.s1, i);
+        ok = in.hit_offset[s] == i;
+      }
       if (!ok) atomicOr(&counters[kCtrError], 1ull);
       if (ok && in.x && !(in.x[i] == row_x[r])) atomicOr(&counters[kCtrError], 8ull);
     }

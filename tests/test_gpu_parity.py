@@ -203,6 +203,17 @@ def test_invalid_rows_are_reported():
     with pytest.raises(C.CatpcError) as e:
         run_gpu(b2)
     assert e.value.status == C.CATPC_E_INVALID
+    # rows fall where each sector starts; a fall inside a later sector of a
+    # batch (not at its start) is reported
+    b3 = synth.batch_workload(seed=7, n_events=1, lo=20, hi=3000)
+    s = 1 + int(np.argmax(np.diff(b3.hit_offset)[1:] > 50))
+    assert b3.hit_offset[s + 1] - b3.hit_offset[s] > 50
+    j = int(b3.hit_offset[s]) + 40
+    b3.row = b3.row.copy()
+    b3.row[j], b3.row[j + 1] = b3.row[j + 1] + 1, b3.row[j]
+    with pytest.raises(C.CatpcError) as e:
+        run_gpu(b3)
+    assert e.value.status == C.CATPC_E_INVALID
     # the context stays usable after an invalid input
     check_batch(synth.sector_workload(seed=9))
 
