@@ -478,44 +478,74 @@ __global__ __launch_bounds__(256) void k_neighbours(Inputs in, Span sp, int R, c
 }
 
 // -------------------------------------------------------------- clean/start
-__global__ __launch_bounds__(kHitsPerBlock) void k_clean_start(Inputs in, Span sp, const int32_t* __restrict__ up,
+// One workgroup per kCleanRounds consecutive blocks of kHitsPerBlock hits:
+// each thread takes one hit of every block, issuing the loads of all its hits
+// before the gathers that depend on them (the kernel is bound by the latency
+// of the chain hit -> link -> link of the linked hit).  Start bits, their
+// per-block counts and every output keep the kHitsPerBlock blocking.
+constexpr int kCleanRounds = 4;
+
+__global__ __launch_bounds__(kHitsPerBlock) void k_clean_start(Inputs in, Span sp, int64_t nblk,
+                                                               const int32_t* __restrict__ up,
                                                                const int32_t* __restrict__ dn,
                                                                int32_t* __restrict__ uc_out,
                                                                int32_t* __restrict__ dc_out, Workspace ws) {
-  const int64_t i = sp.h0 + (int64_t)blockIdx.x * kHitsPerBlock + threadIdx.x;
-  const int s = sector_from(in.hit_offset, sp.s1, ws.blk_sec[blockIdx.x], min(i, sp.h1 - 1));
-  bool start = false;
-  if (i < sp.h1) {
-    const int64_t a = in.hit_offset[s];
-    const int32_t me = (int32_t)(i - a);
-    const int32_t u = up[i], d = dn[i];
-    const int32_t uc = (u >= 0 && dn[a + u] == me) ? u : -1;
-    const int32_t dc = (d >= 0 && up[a + d] == me) ? d : -1;
-    if (dc < 0 && uc >= 0) {
-      const int32_t w = up[a + uc];
-      start = w >= 0 && dn[a + w] == uc;
+  constexpr int K = kCleanRounds;
+  const int64_t hb0 = (int64_t)blockIdx.x * K;
+  int64_t i[K], a[K];
+  int32_t u[K], d[K], uc[K], dc[K];
+  float y[K], z[K];
+  bool on[K], start[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    i[k] = sp.h0 + (hb0 + k) * kHitsPerBlock + threadIdx.x;
+    on[k] = hb0 + k < nblk && i[k] < sp.h1;
+    u[k] = -1; d[k] = -1; a[k] = 0; y[k] = 0.f; z[k] = 0.f;
+    if (on[k]) {
+      const int s = sector_from(in.hit_offset, sp.s1, ws.blk_sec[hb0 + k], i[k]);
+      a[k] = in.hit_offset[s];
+      u[k] = up[i[k]];
+      d[k] = dn[i[k]];
+      y[k] = in.y[i[k]];
+      z[k] = in.z[i[k]];
     }
-    uc_out[i] = uc;
-    dc_out[i] = dc;
-    ChainHit ch;
-    ch.y = in.y[i];
-    ch.z = in.z[i];
-    ch.up = uc;
-    ch.pad = 0;
-    ws.chain[i] = ch;
   }
-  const unsigned long long m = __ballot(start);
-  __shared__ int wc[kHitsPerBlock / 64];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int32_t me = (int32_t)(i[k] - a[k]);
+    uc[k] = (u[k] >= 0 && dn[a[k] + u[k]] == me) ? u[k] : -1;
+    dc[k] = (d[k] >= 0 && up[a[k] + d[k]] == me) ? d[k] : -1;
+  }
+  int32_t w[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) w[k] = (dc[k] < 0 && uc[k] >= 0) ? up[a[k] + uc[k]] : -1;
+#pragma unroll
+  for (int k = 0; k < K; ++k) start[k] = w[k] >= 0 && dn[a[k] + w[k]] == uc[k];
+  __shared__ int wc[K][kHitsPerBlock / 64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) {
-    ws.start_mask[(int64_t)blockIdx.x * (kHitsPerBlock / 64) + wave] = m;
-    wc[wave] = __popcll(m);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (on[k]) {
+      uc_out[i[k]] = uc[k];
+      dc_out[i[k]] = dc[k];
+      ChainHit ch;
+      ch.y = y[k];
+      ch.z = z[k];
+      ch.up = uc[k];
+      ch.pad = 0;
+      ws.chain[i[k]] = ch;
+    }
+    const unsigned long long m = __ballot(start[k]);
+    if (lane == 0) {
+      if (hb0 + k < nblk) ws.start_mask[(hb0 + k) * (kHitsPerBlock / 64) + wave] = m;
+      wc[k][wave] = __popcll(m);
+    }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < K && hb0 + threadIdx.x < nblk) {
     int t = 0;
-    for (int w = 0; w < kHitsPerBlock / 64; ++w) t += wc[w];
-    ws.blk_cnt[blockIdx.x] = t;
+    for (int v = 0; v < kHitsPerBlock / 64; ++v) t += wc[threadIdx.x][v];
+    ws.blk_cnt[hb0 + threadIdx.x] = t;
   }
 }
 
@@ -2197,8 +2227,9 @@ hipError_t launch_clean_start(const Inputs& in, Span sp, const int32_t* up, cons
                               int32_t* dn_c, const Workspace& ws, hipStream_t st) {
   const int64_t n = sp.h1 - sp.h0;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_clean_start, dim3(blocks_for(n, kHitsPerBlock)), dim3(kHitsPerBlock), 0, st, in, sp, up, dn,
-                     up_c, dn_c, ws);
+  const int64_t nblk = blocks_for(n, kHitsPerBlock);
+  hipLaunchKernelGGL(k_clean_start, dim3(blocks_for(nblk, kCleanRounds)), dim3(kHitsPerBlock), 0, st, in, sp, nblk,
+                     up, dn, up_c, dn_c, ws);
   return hipGetLastError();
 }
 
