@@ -1221,14 +1221,29 @@ __global__ __launch_bounds__(256) void k_sel_claim(Inputs in, int S, const int64
   const int64_t t0 = min(toff[s], n), t1 = min(toff[s + 1], n);
   const int RS = row_stride(R);
   bool bad = false, many = false;
+  // A thread's first tracklet keeps its record piece (these rows) in
+  // registers for the second pass; further tracklets read theirs again.
+  constexpr int kQ = kSelRows / 4;
+  const int nq = (r1 - r0 + 3) / 4;
+  int4 keep[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) keep[q] = make_int4(-1, -1, -1, -1);
   for (int64_t slot = t0 + threadIdx.x; slot < t1; slot += blockDim.x) {
     if (!(trk.flags[slot] & 1)) continue;
     const int32_t local = (int32_t)(slot - toff[s]);
     if (local >= (1 << lbits)) { many = true; continue; }
     const unsigned key = sel_weight(trk.n_hits[slot], local, lbits);
     const int4* rec = reinterpret_cast<const int4*>(trk.row_hit + slot * RS + r0);
-    for (int q = 0; q < (r1 - r0 + 3) / 4; ++q) {
-      const int4 v = rec[q];
+    int4 vq[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) vq[q] = q < nq ? rec[q] : make_int4(-1, -1, -1, -1);
+    if (slot == t0 + threadIdx.x) {
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) keep[q] = vq[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int4 v = vq[q];
       const int32_t hv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
@@ -1253,8 +1268,13 @@ __global__ __launch_bounds__(256) void k_sel_claim(Inputs in, int S, const int64
     if (local < (1 << lbits)) {  // past the index limit a tracklet owns nothing
       const unsigned key = sel_weight(trk.n_hits[slot], local, lbits);
       const int4* rec = reinterpret_cast<const int4*>(trk.row_hit + slot * RS + r0);
-      for (int q = 0; q < (r1 - r0 + 3) / 4; ++q) {
-        const int4 v = rec[q];
+      const bool kept = slot == t0 + threadIdx.x;
+      int4 vq[kQ];
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) vq[q] = kept ? keep[q] : q < nq ? rec[q] : make_int4(-1, -1, -1, -1);
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        const int4 v = vq[q];
         const int32_t hv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
