@@ -38,7 +38,7 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
   size_t row_first, hdr, bins, sorted, raw_up, raw_dn, mask, blk_sec, blk_cnt, blk_off, grp_off, start_glob, chain,
-      owner, sel_cnt, sel_loc, sel_grp, sel_mask, mrec, mkey_a, mkey_b, mpair, mover, mslot, mchunk, counters;
+      owner, sel_cnt, sel_local, sel_loc, sel_grp, sel_mask, mrec, mkey_a, mkey_b, mpair, mover, mslot, mchunk, counters;
   size_t total;
 };
 
@@ -63,6 +63,7 @@ Layout plan(int32_t R, int64_t H, int32_t S) {
   const size_t slots = (size_t)(H / 3) + 2;  // tracklets <= H/3: seeds are disjoint chains of >= 3 hits
   L.owner = take(sizeof(unsigned) * (size_t)(H + 1));
   L.sel_cnt = take(sizeof(int32_t) * slots);
+  L.sel_local = take(sizeof(int32_t) * slots);
   L.sel_loc = take(sizeof(int2) * slots);
   L.sel_grp = take(sizeof(longlong2) * (slots / 1024 + 8));
   L.sel_mask = take(sizeof(uint16_t) * slots * (size_t)sel_chunks(R));
@@ -457,6 +458,7 @@ catpc_status catpc_create(int32_t n_rows, const float* row_x, const catpc_params
       w.chain = (ChainHit*)(b + L.chain);
       w.owner = (unsigned*)(b + L.owner);
       w.sel_cnt = (int32_t*)(b + L.sel_cnt);
+      w.sel_local = (int32_t*)(b + L.sel_local);
       w.sel_loc = (int2*)(b + L.sel_loc);
       w.sel_grp = (longlong2*)(b + L.sel_grp);
       w.sel_mask = (uint16_t*)(b + L.sel_mask);

@@ -64,6 +64,7 @@ struct Workspace {
   ChainHit* chain;       // [H] coordinates + cleaned up-link per hit (input order)
   unsigned* owner;               // [H] tracklet selection: weight of the tracklet that keeps each hit (row chunks too dense for LDS)
   int32_t* sel_cnt;              // [H/3 + 2] hits a selected tracklet keeps, or -1
+  int32_t* sel_local;            // [H/3 + 2] sector-local index of each valid tracklet (claim pass)
   int2* sel_loc;                 // [H/3 + 2] track and hit offsets within the slot's group of 1024
   longlong2* sel_grp;            // [(H/3)/1024 + 8] group offsets
   uint16_t* sel_mask;            // [(H/3 + 2) * sel_chunks(R)] kept rows of each valid tracklet, per row chunk

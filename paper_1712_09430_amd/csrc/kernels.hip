@@ -1155,31 +1155,6 @@ __device__ __forceinline__ int64_t sel_slots(const int64_t* toff, int S, int64_t
 // spread over its lanes.  Persistent grid-stride loop over the slots.
 constexpr int kSelLanes = 16;
 
-struct SelTrk {
-  int64_t slot, a;
-  int32_t ns, local;
-  unsigned key;
-  bool on;  // a valid tracklet of this group
-};
-
-__device__ __forceinline__ SelTrk sel_trk(const Inputs& in, int S, const int64_t* toff, const TrackletOut& trk,
-                                          int64_t slot, int64_t n, int lbits) {
-  SelTrk t;
-  t.slot = slot;
-  t.on = slot < n && (trk.flags[slot] & 1) != 0;
-  t.a = 0;
-  t.ns = 0;
-  t.local = 0;
-  t.key = 0;
-  if (t.on) {
-    const int s = sector_of(toff, 0, S, slot);
-    t.a = in.hit_offset[s];
-    t.ns = (int32_t)(in.hit_offset[s + 1] - t.a);
-    t.local = (int32_t)(slot - toff[s]);
-    t.key = sel_weight(trk.n_hits[slot], t.local, lbits);
-  }
-  return t;
-}
 
 // Claim: one workgroup per (sector, chunk of kSelRows rows).  The owner
 // words of the chunk's hits (contiguous, the hits being sorted by row) are
@@ -1288,6 +1263,7 @@ __global__ __launch_bounds__(256) void k_sel_claim(Inputs in, int S, const int64
       }
     }
     ws.sel_mask[slot * nch + ch] = (uint16_t)bits;
+    if (ch == 0) ws.sel_local[slot] = local;  // for the emit pass
   }
 }
 
@@ -1399,10 +1375,9 @@ __global__ __launch_bounds__(256) void k_sel_emit(Inputs in, int S, const int64_
   for (int64_t slot = gtid / kSelLanes; slot < n; slot += stride) {
     const int cnt = ws.sel_cnt[slot];
     if (cnt < 0) continue;  // the 16 lanes of a slot take this branch together
-    const SelTrk t = sel_trk(in, S, toff, trk, slot, n, sel_index_bits(R));
     const longlong2 off = sel_offset(ws, slot);
     if (sub == 0 && off.x < out.track_capacity) {
-      out.track_tracklet[off.x] = t.local;
+      out.track_tracklet[off.x] = ws.sel_local[slot];
       out.track_n_hits[off.x] = cnt;
       out.track_hit_offset[off.x] = off.y;
     }
