@@ -317,8 +317,9 @@ catpc_status catpc_merge_counts(catpc_ctx* ctx, void* stream, int64_t* n_pairs, 
 /* Synchronise `stream` and report the last selection: the number of tracks
  * and of their hits.  CATPC_E_CAPACITY if the output held fewer, or if the
  * tracklet output held only part of the tracklets (then the selection covers
- * only those); CATPC_E_INVALID if a tracklet record named a hit outside its
- * sector; CATPC_E_STATE without a selection since the last track call. */
+ * only those); CATPC_E_INVALID if a tracklet record named a hit that is not
+ * a hit of its sector in the row the entry stands for (such entries are
+ * skipped); CATPC_E_STATE without a selection since the last track call. */
 catpc_status catpc_select_result(catpc_ctx* ctx, void* stream, int64_t* n_tracks, int64_t* n_track_hits);
 
 /* Achievable-peak probes (measurement only, no tracking): a device copy of
