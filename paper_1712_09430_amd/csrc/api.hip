@@ -875,7 +875,7 @@ catpc_status catpc_select_result(catpc_ctx* ctx, void* stream, int64_t* n_tracks
   if (n_tracks) *n_tracks = nt;
   if (n_track_hits) *n_track_hits = nh;
   const unsigned long long err = ctx->host_counters[kCtrError];
-  if (err & 4ull) return fail(CATPC_E_INVALID, "a tracklet record names a hit outside its sector");
+  if (err & 4ull) return fail(CATPC_E_INVALID, "a tracklet record names a hit that is not in the row of its entry");
   if (err & 16ull) return fail(CATPC_E_CAPACITY, "a sector has more tracklets than the selection weights order");
   if (err & 2ull) return fail(CATPC_E_CAPACITY, "the tracklet output holds only part of the tracklets");
   if (nt > ctx->sel_out.track_capacity || nh > ctx->sel_out.hit_capacity)

@@ -1175,6 +1175,7 @@ constexpr int kSelLdsWords = 8192;
 __global__ __launch_bounds__(256) void k_sel_claim(Inputs in, int S, const int64_t* toff, int64_t slots, int R,
                                                    TrackletOut trk, Workspace ws) {
   __shared__ unsigned own[kSelLdsWords];
+  __shared__ int32_t rfc[kSelRows + 1];  // sector-local first hit of the chunk's rows (and the end)
   const int nch = sel_chunks(R);
   const int s = (int)(blockIdx.x / nch);
   const int r0 = (int)(blockIdx.x % nch) * kSelRows;
@@ -1190,6 +1191,7 @@ __global__ __launch_bounds__(256) void k_sel_claim(Inputs in, int S, const int64
   for (int k = threadIdx.x; k < nh; k += blockDim.x) {
     if (lds) own[k] = 0u; else gown[k] = 0u;
   }
+  for (int k = threadIdx.x; k <= r1 - r0; k += blockDim.x) rfc[k] = rf[r0 + k];
   if (!lds) __threadfence();
   __syncthreads();
   const int lbits = sel_index_bits(R);
@@ -1223,9 +1225,10 @@ __global__ __launch_bounds__(256) void k_sel_claim(Inputs in, int S, const int64
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const int32_t h = hv[m];
-        if (h < 0 || 4 * q + m >= r1 - r0) continue;
+        const int rr = 4 * q + m;
+        if (h < 0 || rr >= r1 - r0) continue;
+        if (h < rfc[rr] || h >= rfc[rr + 1]) { bad = true; continue; }  // not a hit of the entry's row
         const int32_t hl = h - h_lo;
-        if (hl < 0 || hl >= nh) { bad = true; continue; }  // not a hit of these rows
         if (lds) atomicMax(&own[hl], key); else atomicMax(&gown[hl], key);
       }
     }
@@ -1253,9 +1256,10 @@ __global__ __launch_bounds__(256) void k_sel_claim(Inputs in, int S, const int64
         const int32_t hv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-          if (hv[m] < 0 || 4 * q + m >= r1 - r0) continue;
+          const int rr = 4 * q + m;
+          if (hv[m] < 0 || rr >= r1 - r0) continue;
+          if (hv[m] < rfc[rr] || hv[m] >= rfc[rr + 1]) continue;  // reported by the first pass
           const int32_t hl = hv[m] - h_lo;
-          if (hl < 0 || hl >= nh) continue;  // reported by the first pass
           // in memory the words were set by atomics at the device level: read them there
           const unsigned o = lds ? own[hl] : __hip_atomic_load(&gown[hl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if (o == key) bits |= 1u << (4 * q + m);

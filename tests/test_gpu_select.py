@@ -145,6 +145,29 @@ def test_capacity_and_state_reports():
     assert e.value.status == C.CATPC_E_STATE
 
 
+def test_record_entries_outside_their_row_are_reported():
+    """A record entry that names a hit of another row, or no hit of the
+    sector, is skipped and reported as CATPC_E_INVALID; after a new track call
+    the selection equals the oracle's again."""
+    from paper_1712_09430_amd import catpc as C
+    b = synth.sector_workload(seed=4, n_tracks=200)
+    tr, hits, out, st, n = run_gpu(b)
+    t = out.tracklets_numpy(n)
+    v = int(np.flatnonzero(t["flags"] & 1)[0])  # a valid tracklet
+    rows = np.flatnonzero(t["row_hit"][v] >= 0)
+    r_a, r_b = int(rows[0]), int(rows[1])  # two rows of one chunk of 16 rows, as a rule
+    for bad in (int(t["row_hit"][v][r_b]), hits.n_hits + 5):
+        out.row_hit[v, r_a] = bad
+        tr.select(hits, out, tr.tracks_output(hits, out))
+        with pytest.raises(C.CatpcError) as e:
+            tr.select_result()
+        assert e.value.status == C.CATPC_E_INVALID
+    tr.track(hits, out)
+    tr.result()
+    _, g, nt, nh = select_gpu(tr, hits, out)
+    check_all(b, g, C.catpc_default_params(), [0])
+
+
 def test_empty_inputs():
     from paper_1712_09430_amd import catpc as C
     from paper_1712_09430_amd.tracker import DeviceHits, Tracker
