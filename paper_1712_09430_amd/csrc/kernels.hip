@@ -114,14 +114,29 @@ __global__ __launch_bounds__(256) void k_row_index(Inputs in, Span sp, int R, co
 }
 
 // -------------------------------------------------------------------- grid
-__device__ __forceinline__ float wave_min(float v) {
-  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
-  return v;
+// Wave minimum / maximum of a float (all 64 lanes active; NaN not expected):
+// floats as order-preserving integer keys, reduced inside each row of 16
+// lanes by DPP moves (quad swaps, half-row and row mirrors), then the four
+// row results read out.  Only the grid shape depends on these values.
+__device__ __forceinline__ int float_key(float v) {
+  const int b = __float_as_int(v);
+  return b ^ ((b >> 31) & 0x7fffffff);
 }
-__device__ __forceinline__ float wave_max(float v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  return v;
+__device__ __forceinline__ float key_float(int k) { return __int_as_float(k ^ ((k >> 31) & 0x7fffffff)); }
+
+template <bool kMax>
+__device__ __forceinline__ int wave_reduce_key(int v) {
+  auto op = [](int x, int y) { return kMax ? max(x, y) : min(x, y); };
+  v = op(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // lanes 1 0 3 2 of each quad
+  v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // lanes 2 3 0 1 of each quad
+  v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));  // mirror inside each half row
+  v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));  // mirror inside each row
+  const int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+  const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+  return op(op(r0, r1), op(r2, r3));
 }
+__device__ __forceinline__ float wave_min(float v) { return key_float(wave_reduce_key<false>(float_key(v))); }
+__device__ __forceinline__ float wave_max(float v) { return key_float(wave_reduce_key<true>(float_key(v))); }
 
 constexpr int kGridKeep = 4;  // 64-hit rounds of a row kept in registers by the grid build
 
