@@ -76,6 +76,30 @@ DEAD_BAND = (70, 8)  # pad rows without clusters in the merging leg's second bat
 MERGE_FLOPS_PER_STEP = 240
 MERGE_FLOPS_PER_PAIR = 110
 PEAK_FP64_TFLOPS = 78.6
+# binary64 operations of the full refit, counted the same way: a state-only transport from the
+# tracklet's first row to the track's first hit (33), a row step with the covariance (240), and a
+# 2-d update (residuals, 2x2 inverse, gain, state, covariance and chi^2: 135)
+REFIT_FLOPS_TRANSPORT = 33
+REFIT_FLOPS_STEP = 240
+REFIT_FLOPS_UPDATE = 135
+
+
+def refit_work(batch, links, trk, tnp, fn):
+    """Row steps of the refit's finished fits, from the tracks, their
+    tracklets and the hits: state-only transports (tracklet first row to the
+    first hit's row), transports with covariance (first to last hit's row),
+    and updates (hits used, from ndf = 2 used - 5)."""
+    ok = fn["flags"] == 1
+    toff = tnp["track_offset"]
+    sec = np.repeat(np.arange(len(toff) - 1), np.diff(toff))
+    nh, h0 = tnp["track_n_hits"], tnp["track_hit_offset"]
+    a = batch.hit_offset[sec]
+    r_first = batch.row[a + tnp["track_hits"][h0]]
+    r_last = batch.row[a + tnp["track_hits"][h0 + nh - 1]]
+    slot = links["tracklet_offset"][sec] + tnp["track_tracklet"]
+    start = trk["first_row"][slot]
+    used = (fn["ndf"] + 5) // 2
+    return (int(np.sum((r_first - start)[ok])), int(np.sum((r_last - r_first)[ok])), int(np.sum(used[ok])))
 
 
 def merge_leg(tr, hits, out, tracks, fits, n_tracks, stream, reps=5):
@@ -471,11 +495,18 @@ def main():
     torch.cuda.synchronize()
     fn = fits.numpy(n_tracks)
     ok = fn["flags"] == 1
-    refit = {"ms": s0.elapsed_time(s1) / 5, "tracks": n_tracks, "done": int(ok.sum()),
+    n_state, n_steps, n_upd = refit_work(batch, out.links_numpy(), out.tracklets_numpy(n_trk),
+                                         tracks.numpy(n_tracks, n_track_hits), fn)
+    refit_ms = s0.elapsed_time(s1) / 5
+    refit_flops = REFIT_FLOPS_TRANSPORT * n_state + REFIT_FLOPS_STEP * n_steps + REFIT_FLOPS_UPDATE * n_upd
+    refit = {"ms": refit_ms, "tracks": n_tracks, "done": int(ok.sum()),
              "chi2_per_ndf_mean": float(np.mean(fn["chi2"][ok] / np.maximum(fn["ndf"][ok], 1))) if ok.any() else None,
+             "state_transports": n_state, "row_steps": n_steps, "updates": n_upd,
+             "fp64_tflops": refit_flops / (refit_ms * 1e-3) / 1e12, "fp64_peak_tflops": PEAK_FP64_TFLOPS,
              "what": "full Kalman refit of the selected tracks: 5x5 covariance, coupled Jacobian, binary64"}
     log(f"[bench] refit: {refit['ms']:.3f} ms, {refit['done']} of {n_tracks} tracks, "
-        f"chi2/ndf {refit['chi2_per_ndf_mean']}")
+        f"chi2/ndf {refit['chi2_per_ndf_mean']}, {n_steps} row steps, {n_upd} updates, "
+        f"{refit['fp64_tflops']:.2f} TFLOP/s binary64")
     # segment merging inside the sectors (after the refit)
     merge = merge_leg(tr, hits, out, tracks, fits, n_tracks, stream)
     log(f"[bench] merge: {merge['ms']:.3f} ms, {merge['links']} links among {n_tracks} tracks, "
