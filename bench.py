@@ -45,8 +45,13 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1712_09430_amd", "csrc", "kernels.hip"
 
 
 def kernels_digest():
+    """SHA-256 of the kernel source followed by the library's build flags."""
+    from paper_1712_09430_amd import build as B
+    h = hashlib.sha256()
     with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+        h.update(f.read())
+    h.update(" ".join(B.FLAGS).encode())
+    return h.hexdigest()
 
 
 def profiled_traffic(workload_name, tuning):

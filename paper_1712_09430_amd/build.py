@@ -2,7 +2,11 @@
 
 hipcc flags: -ffp-contract=off and no fast-math keep every float operation a
 separately rounded IEEE operation (the filter's operation order is part of its
-definition); packed FP32 instructions are disabled.
+definition); packed FP32 instructions are disabled.  The machine scheduler
+orders instructions for instruction-level parallelism (`max-ilp`): the grid
+build, the neighbour search and the tracklet kernel are latency-bound chains,
+and this order is about 1 % faster per step than the occupancy-driven default
+(results are the same: scheduling does not reorder float operations' rounding).
 """
 import os
 import subprocess
@@ -13,7 +17,8 @@ LIB = os.path.join(HERE, "libcatpc.so")
 SOURCES = ["kernels.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-sched-strategy=max-ilp",
+         "-Wall", "-Wno-unused-result"]
 
 
 def build(force: bool = True) -> str:
