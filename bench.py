@@ -89,7 +89,7 @@ REFIT_FLOPS_STEP = 240
 REFIT_FLOPS_UPDATE = 135
 
 
-def refit_work(batch, links, trk, tnp, fn):
+def refit_work(batch, out, n_trk, tnp, fn):
     """Row steps of the refit's finished fits, from the tracks, their
     tracklets and the hits: state-only transports (tracklet first row to the
     first hit's row), transports with covariance (first to last hit's row),
@@ -101,8 +101,8 @@ def refit_work(batch, links, trk, tnp, fn):
     a = batch.hit_offset[sec]
     r_first = batch.row[a + tnp["track_hits"][h0]]
     r_last = batch.row[a + tnp["track_hits"][h0 + nh - 1]]
-    slot = links["tracklet_offset"][sec] + tnp["track_tracklet"]
-    start = trk["first_row"][slot]
+    slot = out.tracklet_offset.cpu().numpy()[sec] + tnp["track_tracklet"]
+    start = out.first_row[:n_trk].cpu().numpy()[slot]
     used = (fn["ndf"] + 5) // 2
     return (int(np.sum((r_first - start)[ok])), int(np.sum((r_last - r_first)[ok])), int(np.sum(used[ok])))
 
@@ -500,8 +500,7 @@ def main():
     torch.cuda.synchronize()
     fn = fits.numpy(n_tracks)
     ok = fn["flags"] == 1
-    n_state, n_steps, n_upd = refit_work(batch, out.links_numpy(), out.tracklets_numpy(n_trk),
-                                         tracks.numpy(n_tracks, n_track_hits), fn)
+    n_state, n_steps, n_upd = refit_work(batch, out, n_trk, tracks.numpy(n_tracks, n_track_hits), fn)
     refit_ms = s0.elapsed_time(s1) / 5
     refit_flops = REFIT_FLOPS_TRANSPORT * n_state + REFIT_FLOPS_STEP * n_steps + REFIT_FLOPS_UPDATE * n_upd
     refit = {"ms": refit_ms, "tracks": n_tracks, "done": int(ok.sum()),
