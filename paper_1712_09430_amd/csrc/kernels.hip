@@ -982,6 +982,23 @@ __device__ __forceinline__ void build_tracklet(const Inputs& in, Span sp, int R,
   const int64_t gi = ws.start_glob[slot];
   const int32_t h0 = (int32_t)(gi - a);
   const int r0 = in.row[gi];
+  int32_t* rec = out.row_hit + o * RS;
+  if (r0 < 1 || r0 > R - 3) {
+    // A start hit has an unlinked hit row below it and two linked rows above
+    // it, so on valid input it lies in rows 1 .. R-3.  Only a row value outside
+    // the sector's rows gets here (the row check has reported the input as
+    // invalid); the tracklet records nothing and writes nothing outside its
+    // own slot.
+    for (int q = 0; q < RS / 8; ++q) chunk_store_none(q, rec);
+    const Trk none = {};
+    store_state(none, o, out);
+    out.start_row[o] = -1;
+    out.first_row[o] = -1;
+    out.last_row[o] = -1;
+    out.n_hits[o] = 0;
+    out.flags[o] = 0;
+    return;
+  }
   const ChainHit c0 = ws.chain[gi];
   const int32_t h1 = c0.up;
   ChainHit nx = ws.chain[a + h1];  // next chain measurement
@@ -990,7 +1007,6 @@ __device__ __forceinline__ void build_tracklet(const Inputs& in, Span sp, int R,
   // has an up-link of its up-link)
   ChainHit nn = nx;
   if (nx.up >= 0) nn = ws.chain[a + nx.up];
-  int32_t* rec = out.row_hit + o * RS;
   const int k0 = r0 >> 3;  // chunk of the start row
   RowChunk k = {chunk_lds + threadIdx.x, (int)blockDim.x, k0};
   chunk_clear(k, k0);
