@@ -29,10 +29,10 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 # Algorithmic work per unit (binary32 operations of the formulas, division and square root count 1):
 NF_BYTES_PER_HIT = 16.0        # y, z in (8 B) + up, down link out (8 B)
-# the other per-hit stages, algorithmic bytes per hit:
-GRID_BYTES_PER_HIT = 32.0      # y, z in (8 B); grid-sorted record (16 B) and two bin-table entries (8 B) out
-CLEAN_BYTES_PER_HIT = 48.0     # links (8 B), the partners' back links (8 B), y, z (8 B) in; cleaned links (8 B)
-                               # and the chain record (16 B) out
+# the other per-hit stages, algorithmic bytes per hit (the method's own data, not this layout's):
+GRID_BYTES_PER_HIT = 24.0      # y, z, row in (12 B); sorted y, z and the permutation out (12 B)
+CLEAN_BYTES_PER_HIT = 36.0     # cleaning: links and the partners' back links in, cleaned links out (24 B);
+                               # start hits: cleaned links in, start bits out (about 12 B)
 ROWIDX_BYTES_PER_HIT = 4.0     # row in
 FLOPS_PER_TRANSPORT = 75.0     # binary32 operations of one helix transport incl. covariance
 FLOPS_PER_UPDATE = 39.0        # two scalar Kalman updates
@@ -222,46 +222,111 @@ def peak_probes(torch, C, dev, stream, log):
             "fma": "2^20 threads x 4096 iterations x 8 independent binary32 FMA chains (non-packed)"}
 
 
+def truth_pulls(b, t, valid):
+    """Pulls (p - p_true) / sqrt(C_ii) of y, z, sin phi, tan lambda, q/pT at
+    x_ref over truth-matched tracklets: at least 90 % of the hits from one
+    generated track, whose own hit sits in the tracklet's first row (the
+    generator's true position there is the truth at x_ref)."""
+    tr0 = b.tracks[0]
+    names = ("y", "z", "sinphi", "tanl", "qpt")
+    rows = []
+    for k in np.flatnonzero(valid):
+        rh = t["row_hit"][k][:b.n_rows]
+        hits = rh[rh >= 0]
+        lab = b.label[hits]
+        vals, cnt = np.unique(lab, return_counts=True)
+        L = vals[cnt.argmax()]
+        h = rh[t["first_row"][k]]
+        if L < 0 or cnt.max() < 0.9 * len(hits) or h < 0 or b.label[h] != L:
+            continue
+        truth = np.array([b.truth["y_true"][h], b.truth["z_true"][h], b.truth["sinphi_true"][h],
+                          math.sinh(tr0["eta"][L]), tr0["q"][L] / tr0["pt"][L]])
+        var = t["cov"][k][[0, 2, 5, 9, 14]].astype(np.float64)
+        if np.all(var > 0):
+            rows.append((t["param"][k].astype(np.float64) - truth) / np.sqrt(var))
+    p = np.array(rows).reshape(-1, 5)
+    return {n: {"mean": float(p[:, i].mean()), "rms": float(np.sqrt((p[:, i] ** 2).mean())), "n": len(p)}
+            for i, n in enumerate(names)} | {"matched_tracklets": len(p)}
+
+
 def precision_leg(torch, tuning, log):
-    """The precision form on the one-sector workload (200 tracks): tracklets
-    whose binary32 covariance fails the SPD check, tracklets refitted with a
-    binary64 covariance, and pulls of y, z, sin(phi) at x_ref against the
-    generator's true track position at the tracklet's innermost hit (signal
-    hits only), for the binary32 form and the precision form."""
+    """The precision form (binary32 filter; binary64 covariance refit only for
+    tracklets whose binary32 covariance fails the SPD check) on the
+    one-sector workload (200 tracks) and on the same sector with precise
+    clusters (smear and fit error 3e-4 cm, where binary32 pivots do fail):
+    failures, refits, and pulls over truth-matched tracklets.  The GPU
+    tracklets are kept for the oracle leg's binary64 parameter check."""
     import synth
     from paper_1712_09430_amd import catpc as C
     from paper_1712_09430_amd.tracker import DeviceHits, Tracker
-    b = synth.sector_workload(seed=1, n_tracks=200, truth=True)
-    hits = DeviceHits(b.y, b.z, b.row, b.hit_offset, "cuda:0")
-    rep = {"workload": "sector: one sector, 200 tracks, 159 pad rows, seed 1", "n_hits": hits.n_hits}
-    for prec in (0, 1):
-        p = C.catpc_default_params()
-        p.precision = prec
-        tr = Tracker(b.row_x, hits.n_hits, hits.n_sectors, params=p)
-        tr.set_tuning(dict(tuning, use_graph=0))
-        out = tr.output(hits)
-        tr.track(hits, out)
-        st, n = tr.result()
-        t = out.tracklets_numpy(n)
-        fl = t["flags"]
-        valid = (fl & C.FLAG_VALID) != 0
-        first_hit = t["row_hit"][np.arange(n), t["first_row"]]
-        sig = valid & (first_hit >= 0)
-        sig[sig] &= b.label[first_hit[sig]] >= 0
-        h = first_hit[sig]
-        pulls = {}
-        for name, k, ci, tk in (("y", 0, 0, "y_true"), ("z", 1, 2, "z_true"), ("sinphi", 2, 5, "sinphi_true")):
-            var = t["cov"][sig, ci].astype(np.float64)
-            ok = var > 0
-            pv = (t["param"][sig, k].astype(np.float64)[ok] - b.truth[tk][h][ok]) / np.sqrt(var[ok])
-            pulls[name] = {"mean": float(pv.mean()), "rms": float(np.sqrt((pv ** 2).mean())), "n": int(ok.sum())}
-        rep[f"precision_{prec}"] = {"tracklets": int(n), "valid": int(valid.sum()),
-                                    "spd_failures": int(((fl & C.FLAG_SPD_FAIL) != 0).sum()),
-                                    "refits": int(((fl & C.FLAG_REFIT64) != 0).sum()), "pulls": pulls}
-        tr.close()
-    log(f"[bench] precision: SPD failures {rep['precision_0']['spd_failures']}, "
-        f"refits {rep['precision_1']['refits']} of {rep['precision_1']['tracklets']} tracklets")
-    return rep
+    rep, keep = {}, {}
+    for name, seed, sigma in (("sector", 1, 0.1), ("sector_precise_clusters", 11, 3e-4)):
+        b = synth.sector_workload(seed=seed, n_tracks=200, truth=True, sigma=sigma)
+        hits = DeviceHits(b.y, b.z, b.row, b.hit_offset, "cuda:0")
+        r = {"workload": f"sector: one sector, 200 tracks, 159 pad rows, seed {seed}, cluster smear and fit "
+                         f"error {sigma:g} cm", "n_hits": hits.n_hits}
+        for prec in (0, 1):
+            p = C.catpc_default_params()
+            p.precision = prec
+            p.sigma_y = p.sigma_z = sigma
+            tr = Tracker(b.row_x, hits.n_hits, hits.n_sectors, params=p)
+            tr.set_tuning(dict(tuning, use_graph=0))
+            out = tr.output(hits)
+            tr.track(hits, out)
+            st, n = tr.result()
+            t = out.tracklets_numpy(n)
+            fl = t["flags"]
+            valid = (fl & C.FLAG_VALID) != 0
+            r[f"precision_{prec}"] = {"tracklets": int(n), "valid": int(valid.sum()),
+                                      "spd_failures": int(((fl & C.FLAG_SPD_FAIL) != 0).sum()),
+                                      "refits": int(((fl & C.FLAG_REFIT64) != 0).sum()),
+                                      "pulls_truth_matched": truth_pulls(b, t, valid)}
+            keep[(name, prec)] = (b, t, p)
+            tr.close()
+        rep[name] = r
+        log(f"[bench] precision {name}: SPD failures {r['precision_0']['spd_failures']}, "
+            f"refits {r['precision_1']['refits']} of {r['precision_1']['tracklets']} tracklets")
+    rep["pull_definition"] = ("(p - p_true) / sqrt(C_ii) at x_ref over valid tracklets with >= 90 % of their hits "
+                              "from one generated track whose own hit is in the tracklet's first row")
+    return rep, keep
+
+
+STRICT_ABS = np.array([1e-3, 1e-3, 0.0, 0.0, 0.0])
+STRICT_REL = np.array([0.0, 0.0, 1e-4, 1e-4, 1e-4])
+STRICT_FLOOR = np.array([1.0, 1.0, 1.0, 1.0, 0.1])
+
+
+def parameter_check(items):
+    """ORACLE LEG: binary32 GPU parameters against the binary64 oracle refit of
+    the same hits (y, z within 1e-3 cm; sin phi, tan lambda within 1e-4 of
+    max(|ref|, 1); q/pT within 1e-4 of max(|ref|, 0.1)).  items: (y, z,
+    row_x, tracklet dict, params) per sector.  Returns the fraction of
+    compared tracklets with all five inside, the per-parameter maximum
+    deviation, and the q/pT values outside (count, largest deviation in units
+    of their binary64 standard error)."""
+    import oracle
+    devs, sigq = [], []
+    for y, z, row_x, t, p in items:
+        op = oracle.Params(bz=p.bz, sigma_y=p.sigma_y, sigma_z=p.sigma_z)
+        if len(t["flags"]) == 0:
+            continue
+        r = oracle.refit(y, z, row_x, t["row_hit"][:, :len(row_x)], t["start_row"], op, "f64")
+        good = ((t["flags"] & 1) != 0) & ((r["flags"] & 1) != 0)
+        devs.append(np.abs(t["param"][good].astype(np.float64) - r["param"][good]) /
+                    (STRICT_ABS + STRICT_REL * np.maximum(np.abs(r["param"][good]), STRICT_FLOOR)))
+        sigq.append(np.abs(t["param"][good, 4].astype(np.float64) - r["param"][good, 4]) /
+                    np.sqrt(r["cov"][good, 14]))
+    d = np.concatenate(devs) if devs else np.zeros((0, 5))
+    sq = np.concatenate(sigq) if sigq else np.zeros(0)
+    inside = np.all(d <= 1.0, axis=1)
+    outq = d[:, 4] > 1.0
+    return {"tracklets": int(len(d)), "fraction_strict": float(inside.mean()) if len(d) else None,
+            "max_over_bound": {k: float(d[:, i].max()) if len(d) else None
+                               for i, k in enumerate(("y", "z", "sinphi", "tanl", "qpt"))},
+            "qpt_outside": int(outq.sum()),
+            "qpt_outside_max_dev_over_sigma": float(sq[outq].max()) if outq.any() else None,
+            "bound": "y, z 1e-3 cm; sin phi, tan lambda 1e-4 max(|ref|, 1); q/pT 1e-4 max(|ref|, 0.1); "
+                     "max_over_bound = largest deviation / its bound"}
 
 
 def scheduling_leg(batch, tuning, hits_total, log):
@@ -280,6 +345,41 @@ def scheduling_leg(batch, tuning, hits_total, log):
         out[name] = {"ms_per_step": ms, "hits_per_s": hits_total / (ms * 1e-3)}
         log(f"[bench] scheduling {name}: {ms:.2f} ms/step")
     return out
+
+
+def config_lines(torch, tuning, seed, log, reps=20, plain_reps=5):
+    """The single-sector workload (200 tracks) and the full central event
+    (10k tracks, 36 sectors), each in the batched form (graph replay, median
+    of `reps` HIP-event-timed steps after 3 warm-up steps) and in the plain
+    form (per-sector launches, median of `plain_reps`)."""
+    from paper_1712_09430_amd.tracker import DeviceHits, Tracker
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name in ("sector", "event"):
+        b, desc = workload(name, seed)
+        hits = DeviceHits(b.y, b.z, b.row, b.hit_offset, "cuda:0")
+        tr = Tracker(b.row_x, hits.n_hits, hits.n_sectors, tuning=tuning)
+        out = tr.output(hits)
+        line = {"workload": desc, "n_hits": int(hits.n_hits), "n_sectors": int(hits.n_sectors)}
+        for form, k in (("batch", reps), ("plain", plain_reps)):
+            for _ in range(3):
+                tr.track(hits, out, form)
+            st, n = tr.result()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
+            ev[0].record(stream)
+            for i in range(k):
+                tr.track(hits, out, form)
+                ev[i + 1].record(stream)
+            torch.cuda.synchronize()
+            ms = float(np.median([ev[i].elapsed_time(ev[i + 1]) for i in range(k)]))
+            line[form] = {"ms_per_step": ms, "hits_per_s": hits.n_hits / (ms * 1e-3), "steps": k,
+                          "n_tracklets": int(n), "status": int(st)}
+            log(f"[bench] {name} {form}: {ms:.3f} ms/step, {line[form]['hits_per_s']:.4g} hits/s")
+        line["batched_over_plain"] = line["batch"]["hits_per_s"] / line["plain"]["hits_per_s"]
+        res[name] = line
+        tr.close()
+        del hits, out
+    return res
 
 
 LINEARITY_TRACKS = (250, 500, 1000, 2000, 4000, 8000, 16000)
@@ -348,7 +448,17 @@ def serving_leg(args, tuning, log):
     stun = stun or tuning
     res = serve.serve(src, tuning=stun, warmup_events=args.serve_warmup)
     log(f"[bench] serving: p50 {res['p50_ms']:.3f} ms, p99 {res['p99_ms']:.3f} ms, {res['hits_per_s']:.4g} hits/s, "
-        f"{res['batches']} batches, {res['slots']} slots")
+        f"{res['batches']} batches, {res['slots']} slots, peak in flight "
+        f"{res['peak_in_flight_bytes'] / 2**20:.0f} MiB, {res['deferred_events']} deferred")
+    # the same stream (first 3000 events) under a budget of twice the largest event's footprint: the
+    # budget, not the slot count, then decides admissions
+    n_tight = min(3000, args.serve_events)
+    src_t = serve.EventStream(pool, order[:n_tight], arrival[:n_tight], pool[0].row_x)
+    tight_budget = 2 * res["largest_event_footprint_bytes"]
+    tight = serve.serve(src_t, tuning=stun, warmup_events=min(args.serve_warmup, n_tight // 10),
+                        hbm_budget=tight_budget)
+    log(f"[bench] serving, budget {tight_budget / 2**20:.0f} MiB: p50 {tight['p50_ms']:.3f} ms, "
+        f"p99 {tight['p99_ms']:.3f} ms, {tight['slots']} slots, {tight['deferred_events']} deferred")
     # the same stream with every event waiting from the start: the server's
     # saturated throughput (H2D, hot path and D2H of overlapping batches)
     sat = serve.serve(src, tuning=stun, warmup_events=0, realtime=False)
@@ -357,7 +467,19 @@ def serving_leg(args, tuning, log):
             "events": res["n_events"], "warmup_events": args.serve_warmup, "rate_hz": args.serve_rate,
             "batches": res["batches"], "mean_batch_events": res["mean_batch_events"], "slots": res["slots"],
             "hbm_budget_gib": res["hbm_budget_bytes"] / 2**30,
-            "slot_footprint_gib": res["slot_footprint_bytes"] / 2**30,
+            "slot_reserved_gib": res["slot_reserved_bytes"] / 2**30,
+            "footprint_model": "per batch: input + 3 x input (internal) + outputs (links, start list, "
+                               "estimated tracklet records)",
+            "full_batch_footprint_gib": res["full_batch_footprint_bytes"] / 2**30,
+            "largest_event_footprint_mib": res["largest_event_footprint_bytes"] / 2**20,
+            "peak_in_flight_mib": res["peak_in_flight_bytes"] / 2**20,
+            "deferred_events": res["deferred_events"],
+            "tight_budget": {"budget_mib": tight_budget / 2**20, "events": tight["n_events"],
+                             "slots": tight["slots"], "p50_ms": tight["p50_ms"], "p99_ms": tight["p99_ms"],
+                             "hits_per_s": tight["hits_per_s"], "deferred_events": tight["deferred_events"],
+                             "peak_in_flight_mib": tight["peak_in_flight_bytes"] / 2**20,
+                             "what": "first 3000 events of the same stream, budget = twice the largest event's "
+                                     "footprint"},
             "latency": "arrival to results in host memory (H2D + hot path + D2H)",
             "saturated_hits_per_s": sat["hits_per_s"], "saturated_batches": sat["batches"],
             "late_fetches": res["late_fetches"],
@@ -372,7 +494,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch64")
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--cpu-hits", type=float, default=3e7, help="oracle sample size for cpu_baseline (all threads)")
     ap.add_argument("--cpu-hits-1", type=float, default=1.5e6, help="oracle sample size on one thread")
     ap.add_argument("--cpu-hits-4", type=float, default=6e6, help="oracle sample size on four threads")
@@ -380,6 +502,8 @@ def main():
     ap.add_argument("--no-precision", action="store_true", help="skip the precision-form report")
     ap.add_argument("--no-scheduling", action="store_true", help="skip the scheduling baselines")
     ap.add_argument("--no-linearity", action="store_true", help="skip the time-vs-hits check")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the one-sector and full-event lines (batched and plain)")
     ap.add_argument("--no-dead-band", action="store_true",
                     help="skip the merging leg's second batch (same events, 8 dead pad rows)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -420,7 +544,9 @@ def main():
         cached = autotune.cached_tuning()
         if cached is not None:
             tr.set_tuning(cached)
-            tuning_src = "autotuner cache " + os.path.basename(autotune.DEFAULT_CACHE)
+            tuning_src = "autotuner cache " + os.path.basename(autotune.DEFAULT_CACHE) + (
+                " (tuned on these kernels)" if autotune.cache_is_current() else
+                " (tuned on an earlier kernel source)")
     elif args.tuning != "default":
         tr.set_tuning(json.load(open(args.tuning)))
         tuning_src = args.tuning
@@ -550,7 +676,9 @@ def main():
              "algorithmic_flops": float(flops), "work_counts": work.tolist()}
     rl_tc["frac"] = rl_tc["achieved"] / rl_tc["peak"]
     nf_bytes = NF_BYTES_PER_HIT * hits.n_hits
-    rl_nf = {"kernel": "k_neighbours", "bound": "hbm", "achieved": nf_bytes / (nf_ms * 1e-3) / 1e9,
+    # the neighbour stage: the LDS-staged kernel, or (nf_lds_kb = 0) the in-place one
+    nf_kernel = "k_nf_flat" if tuning["nf_lds_kb"] == 0 else "k_neighbours"
+    rl_nf = {"kernel": nf_kernel, "bound": "hbm", "achieved": nf_bytes / (nf_ms * 1e-3) / 1e9,
              "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None, "launch_ms": nf_ms,
              "algorithmic_bytes": nf_bytes}
     rl_nf["frac"] = rl_nf["achieved"] / rl_nf["peak"]
@@ -565,10 +693,12 @@ def main():
         others[kern]["frac"] = others[kern]["achieved"] / HBM_PEAK_GBS
     traffic = profiled_traffic(args.workload, tuning)
     for rl in (rl_tc, rl_nf, *others.values()):
-        t = traffic.get(rl["kernel"])
-        if t:
-            rl["traffic"] = t["fetch_bytes"] + t["write_bytes"]
-            rl["traffic_fetch"], rl["traffic_write"] = t["fetch_bytes"], t["write_bytes"]
+        parts = [traffic.get(kn) for kn in rl["kernel"].split("+")]
+        if all(parts):
+            f = sum(t["fetch_bytes"] for t in parts)
+            wr = sum(t["write_bytes"] for t in parts)
+            rl["traffic"] = f + wr
+            rl["traffic_fetch"], rl["traffic_write"] = f, wr
             rl["traffic_source"] = os.path.relpath(TRAFFIC_PROFILE, ROOT)
     dominant = rl_tc if tc_ms >= nf_ms else rl_nf
 
@@ -578,15 +708,17 @@ def main():
         tr.track(hits, out, "plain")
         tr.result()
         torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(args.plain_steps):
+        pev = [torch.cuda.Event(enable_timing=True) for _ in range(args.plain_steps + 1)]
+        pev[0].record(stream)
+        for k in range(args.plain_steps):
             tr.track(hits, out, "plain")
-        e1.record(stream)
+            pev[k + 1].record(stream)
         torch.cuda.synchronize()
         st, n2 = tr.result()
-        pms = e0.elapsed_time(e1) / args.plain_steps
+        pms = float(np.median([pev[k].elapsed_time(pev[k + 1]) for k in range(args.plain_steps)]))
         plain = {"hits_per_s": hits.n_hits / (pms * 1e-3), "ms_per_step": pms, "steps": args.plain_steps,
-                 "launches_per_step": 8 * hits.n_sectors + 1, "status": int(st), "n_tracklets": n2}
+                 "timing": "median of the HIP-event-timed steps", "launches_per_step": 8 * hits.n_sectors + 1,
+                 "status": int(st), "n_tracklets": n2}
         log(f"[bench] plain: {pms:.3f} ms/step, {plain['hits_per_s']:.4g} hits/s")
 
     scheduling = None
@@ -595,6 +727,8 @@ def main():
         scheduling["plain_1_queue"] = {"ms_per_step": plain["ms_per_step"], "hits_per_s": plain["hits_per_s"]} \
             if plain else None
         scheduling["batch_1_instance"] = {"ms_per_step": ms_step, "hits_per_s": value}
+        scheduling["note"] = ("HIP maps a process's streams onto GPU_MAX_HW_QUEUES hardware queues (4 here, the "
+                              "default), so the 8 streams of the 8-queue form share 4 hardware queues")
 
     serving = None
     if args.serve_events > 0:
@@ -608,9 +742,13 @@ def main():
             rl["achievable_peak"] = peaks[key]
             rl["frac_of_achievable"] = rl["achieved"] / peaks[key]
 
-    precision = None
+    precision, prec_keep = None, {}
     if not args.no_precision:
-        precision = precision_leg(torch, tuning, log)
+        precision, prec_keep = precision_leg(torch, tuning, log)
+
+    configs = None
+    if not args.no_configs:
+        configs = config_lines(torch, tuning, args.seed, log)
 
     linearity = None
     if not args.no_linearity:
@@ -629,6 +767,30 @@ def main():
         log(f"[bench] oracle, four threads: {four['value']:.4g} hits/s")
         cpu["four_threads"] = {"value": four["value"], "sample": four["sample"]}
         cpu["gpu_over_four_threads"] = value / four["value"]
+        # the same oracle leg, untimed: binary32 GPU parameters against the
+        # binary64 oracle refit of their hits (config 3 and sampled sectors of
+        # this batch, every k-th by size)
+        checks = {}
+        for (name, prec), (b1, t1, p1) in prec_keep.items():
+            if (name, prec) in (("sector", 0), ("sector_precise_clusters", 1)):
+                checks[f"{name}_precision_{prec}"] = parameter_check([(b1.y, b1.z, b1.row_x, t1, p1)])
+        if args.workload == "batch64":
+            sizes = np.diff(batch.hit_offset)
+            pick = sorted(np.argsort(-sizes, kind="stable")[::16].tolist())
+            off = out.tracklet_offset.cpu().numpy()
+            items = []
+            for sct in pick:
+                a0, a1 = int(off[sct]), int(off[sct + 1])
+                sec = batch.sector(sct)
+                t1 = {"param": out.param[a0:a1].cpu().numpy(), "row_hit": out.row_hit[a0:a1].cpu().numpy(),
+                      "start_row": out.start_row[a0:a1].cpu().numpy(), "flags": out.flags[a0:a1].cpu().numpy()}
+                items.append((sec["y"], sec["z"], batch.row_x, t1, C.catpc_default_params()))
+            checks[f"batch64_sample_{len(pick)}_sectors"] = parameter_check(items)
+        for k, v in checks.items():
+            log(f"[bench] parameters vs binary64 oracle, {k}: {v['fraction_strict']} of {v['tracklets']} strict")
+        if precision is not None:
+            precision["parameter_check"] = checks | {"computed_by": "the oracle leg (binary64 refit of the GPU "
+                                                                   "tracklets' hits)"}
         cpu["paper_context"] = ("the paper quotes its GPU tracker at about 10x four CPU cores on its own Run-1 "
                                 "hardware (Sec. 1); context only, different hardware, code and data")
         cpu["nproc"] = os.cpu_count()
@@ -643,8 +805,8 @@ def main():
                       "tuning": tuning, "tuning_source": tuning_src},
            "plain": plain, "batched_over_plain": (value / plain["hits_per_s"]) if plain else None,
            "serving": serving, "stages_ms": stages, "roofline": {k: v for k, v in dominant.items() if k != "kernel"} |
-           {"kernel": dominant["kernel"]}, "rooflines": {"k_tracklets": rl_tc, "k_neighbours": rl_nf, **others},
-           "selection": sel, "refit": refit, "merge": merge, "scheduling": scheduling, "achievable_peaks": peaks, "precision": precision, "linearity": linearity, "cpu_baseline": cpu}
+           {"kernel": dominant["kernel"]}, "rooflines": {"k_tracklets": rl_tc, "neighbours": rl_nf, **others},
+           "selection": sel, "refit": refit, "merge": merge, "scheduling": scheduling, "achievable_peaks": peaks, "precision": precision, "configs": configs, "linearity": linearity, "cpu_baseline": cpu}
     print(json.dumps(res), flush=True)
 
 

@@ -75,7 +75,9 @@ typedef struct {
   int32_t tc_waves_per_cu; /* resident waves per CU of the persistent tracklet kernel [20] */
   int32_t use_graph;     /* 1: replay the batched stage chain as a captured hipGraph [1] */
   int32_t nf_rows;       /* pad rows per neighbour-finder workgroup (row chunk) [4] */
-  int32_t nf_lds_kb;     /* LDS budget (KiB) for staging a row chunk and its two neighbour rows [32] */
+  int32_t nf_lds_kb;     /* LDS budget (KiB) for staging a row chunk and its two neighbour rows (a chunk that does
+                            not fit is searched in place); 0: every hit is searched in place, one thread per hit in
+                            grid order (a separate kernel) [32] */
   int32_t tc_xcd;        /* 1: tracklet slots split into one contiguous part per die, each die starting on its
                             own part (L2 locality) [1] */
   int32_t tc_occupancy;  /* resident waves per SIMD the tracklet kernel's registers are fitted for:
@@ -178,6 +180,21 @@ typedef struct {
 
 typedef struct catpc_ctx catpc_ctx;
 
+/* Detector geometry (Sec. 2: the TPC's two halves are each divided into 18
+ * trapezoidal sectors, every sector tracked on its own in its own frame, the
+ * hits lying on the planes of its pad rows).  The sector frame: x along the
+ * normal of the pad rows, y across them, z along the beam axis (the same
+ * axis in every frame).  Sector s (0 <= s < 2 * sectors_per_side) sits on
+ * side A (z >= 0) for s < sectors_per_side, else on side C, rotated about the
+ * beam axis by alpha_s = ((s mod sectors_per_side) + 1/2) * 2 pi /
+ * sectors_per_side; a point of the sector frame is (X, Y, Z) = (x cos alpha -
+ * y sin alpha, x sin alpha + y cos alpha, z) in the global frame. */
+typedef struct {
+  int32_t n_rows;            /* pad rows per sector, 3 .. 4096 */
+  const float* row_x;        /* host [n_rows]: x of each pad-row plane, cm, positive, strictly ascending */
+  int32_t sectors_per_side;  /* sectors in each half of the TPC (18); 0 takes 18 */
+} catpc_geometry;
+
 /* Defaults of the method parameters and of the tuning. */
 void catpc_default_params(catpc_params* p);
 void catpc_default_tuning(catpc_tuning* t);
@@ -190,13 +207,37 @@ int32_t catpc_row_stride(int32_t n_rows);
 /* Device workspace bytes catpc_create allocates for these maximum sizes. */
 size_t catpc_workspace_bytes(int32_t n_rows, int64_t max_hits, int32_t max_sectors);
 
-/* Create a tracker on the current HIP device.  row_x: host [n_rows], x of
- * each pad row (cm, ascending), 3 <= n_rows <= 4096; max_hits / max_sectors
- * bound every later call.  Allocates the workspace once.  Returns
- * CATPC_E_INVALID for bad sizes, CATPC_E_HIP if allocation fails. */
-catpc_status catpc_create(int32_t n_rows, const float* row_x, const catpc_params* params, int64_t max_hits,
+/* Create a tracker on the current HIP device for the geometry `geom` (its
+ * row_x is copied) and the method parameters `params` (field, cluster
+ * errors, cuts).  One tracker instance holds internal buffers sized once for
+ * the largest input it will see (Sec. 4.1: the tracker's internal memory is
+ * about three times the input): max_hits / max_sectors bound every later
+ * call, and no later call allocates.  Returns CATPC_E_INVALID for a NULL or
+ * inconsistent argument (n_rows outside [3, 4096], row_x not positive and
+ * strictly ascending, sectors_per_side < 0, sizes out of range, bad
+ * parameters), CATPC_E_HIP if allocation fails; *out is NULL on failure. */
+catpc_status catpc_create(const catpc_geometry* geom, const catpc_params* params, int64_t max_hits,
                           int32_t max_sectors, catpc_ctx** out);
 void catpc_destroy(catpc_ctx* ctx);
+
+/* Frame of sector `sector_id` (host call, no device needed): its rotation
+ * about the beam axis, rad, and side (+1 A, -1 C), as stated at
+ * catpc_geometry.  CATPC_E_INVALID for a NULL argument or a sector id outside
+ * [0, 2 * sectors_per_side). */
+catpc_status catpc_sector_frame(const catpc_geometry* geom, int32_t sector_id, double* alpha, int32_t* side);
+
+/* Tracklet (or track) parameters of sector `sector_id` in the global frame
+ * (host call on host arrays, not part of the hot path; Sec. 2: tracking runs
+ * in each sector's frame, the later steps across sectors need the global
+ * one).  For each of the n entries: x[i] and param[i][0..4] = (y, z, sin phi,
+ * tan lambda, q/pT) in the sector frame give out[i][0..5] = (X, Y, Z, phi,
+ * tan lambda, q/pT): the global position, the global azimuth of the momentum
+ * (asin(sin phi) + alpha, in (-pi, pi]), and the unchanged dip and signed
+ * curvature parameters.  Computed in binary64.  CATPC_E_INVALID for NULL
+ * arrays, n < 0, a sector id out of range, or |sin phi| > 1 (that entry's
+ * output is NaN; the others are written). */
+catpc_status catpc_to_global(const catpc_geometry* geom, int32_t sector_id, int64_t n, const float* x,
+                             const float* param, double* out);
 
 catpc_status catpc_set_params(catpc_ctx* ctx, const catpc_params* params);
 catpc_status catpc_set_tuning(catpc_ctx* ctx, const catpc_tuning* tuning);
@@ -205,16 +246,27 @@ catpc_status catpc_get_tuning(const catpc_ctx* ctx, catpc_tuning* tuning);
 /* Batched form: the whole hot path (row index and grid build, neighbour
  * finding, link cleaning and start hits, tracklet construction, optional
  * precision refit) over all sectors of the input in a fixed chain of
- * launches, independent of the number of sectors; replayed as a hipGraph
- * when tuning.use_graph is set and the arguments match the captured chain.
- * Tracklet slots [0, tracklet_capacity) are written; see catpc_result. */
+ * launches, independent of the number of sectors (Sec. 3: one sector alone
+ * does not hold enough parallel work for the GPU, and sectors are
+ * independent; Sec. 3.2: several events are processed on the GPU at once);
+ * replayed as a hipGraph when tuning.use_graph is set and the arguments
+ * match the captured chain.  Tracklet slots [0, tracklet_capacity) are
+ * written; see catpc_result.  CATPC_E_INVALID (outputs untouched) for NULL
+ * arguments, sizes beyond those given to catpc_create, n_hits !=
+ * hit_offset[n_sectors] when hit_offset_host is given, or misaligned
+ * row_hit; CATPC_E_HIP if a launch fails. */
 catpc_status catpc_track_batch(catpc_ctx* ctx, const catpc_input* in, const catpc_output* out, void* stream);
 
-/* Plain form: the same stages launched sector by sector (input.hit_offset_host
- * required).  Output identical to catpc_track_batch. */
+/* Plain form: the same stages launched sector by sector (Sec. 3, Fig. 3:
+ * the earlier scheme processed one sector per kernel launch) -- the baseline
+ * the batched form is measured against.  input.hit_offset_host is required
+ * (CATPC_E_INVALID without it); errors as catpc_track_batch.  Output
+ * identical to catpc_track_batch. */
 catpc_status catpc_track_plain(catpc_ctx* ctx, const catpc_input* in, const catpc_output* out, void* stream);
 
-/* Synchronise the stream and report: CATPC_E_INVALID if the device found hits
+/* Synchronise the stream and report (Sec. 3.1: the number of tracks is not
+ * known in advance; the host reads the count back and fetches what did not
+ * fit): CATPC_E_INVALID if the device found hits
  * that are not row-sorted or a row out of range (outputs undefined), else
  * CATPC_E_CAPACITY if the last track call found more tracklets than its
  * output slots, else CATPC_OK.  *n_tracklets (may be NULL) receives the total
@@ -254,9 +306,9 @@ catpc_status catpc_work_counts(catpc_ctx* ctx, void* stream, int64_t* counts);
  * Used to check that the device rounds like the host. */
 catpc_status catpc_fp32_probe(int32_t op, const float* a, const float* b, float* out, int64_t n, void* stream);
 
-/* Tracklet selection (Sec. 2 item 2: of several seeds followed along the
- * same track segment the best instance is kept and the others are removed;
- * Sec. 3: it runs after the tracklet construction, many sectors per launch).
+/* Tracklet selection (Sec. 2 item 2: duplicate tracklets -- several seeds
+ * that grew into the same segment -- are reduced to one per segment; Sec. 3:
+ * this step follows the tracklet construction, many sectors per launch).
  * Reads the tracklets of a finished track call (`trk`: tracklet_offset,
  * flags, n_hits, row_hit) for the hits `in`.  Every hit goes to the heaviest
  * valid tracklet that lists it (weight: hit count, then the smaller

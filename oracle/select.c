@@ -2,9 +2,9 @@
  * CPU oracle: tracklet selection (integer work).  Test infrastructure only;
  * see oracle.h.
  *
- * Sec. 2 item 2: when several seeds were followed along the same track
- * segment, the best instance is kept and the others are removed; Sec. 3: the
- * selection runs after the tracklet construction, several sectors per launch.
+ * Sec. 2 item 2: duplicate tracklets (several seeds grown into one segment)
+ * are reduced to one per segment; Sec. 3: this step follows the tracklet
+ * construction, several sectors per launch.
  * Reading used here (one pass, order-independent):
  *  - only valid tracklets (flag VALID: at least min_hits hits) take part;
  *  - a tracklet's weight is its hit count; between equal counts the smaller

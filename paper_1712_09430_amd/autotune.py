@@ -2,10 +2,11 @@
 
 A joint grid over the tracklet kernel's register fit, resident waves per CU
 then a coordinate search over the other catpc_tuning
-fields (grid-bin occupancy, block sizes, row chunks, LDS staging), timing the replayed hipGraph with HIP
-events on the caller's stream.  The result never changes the output (the
+fields (grid-bin occupancy, block sizes, row chunks, LDS staging), timing the replayed hipGraph
+with HIP events on the caller's stream.  The result never changes the output (the
 kernels' results do not depend on these values); it is written to a JSON cache
-keyed by the device architecture, which bench.py and the serving loop read.
+keyed by the device architecture, with the digest of the kernel source and
+build flags it was tuned on, which bench.py and the serving loop read.
 
 The serving form has its own optimum (one or a few events per launch, where
 the latency of the tracklet waves matters more than the fill of the GPU):
@@ -36,7 +37,7 @@ SPACE = {
     "tc_xcd": [0, 1],
     "tc_block": [64, 128, 256],
     "bin_hits": [0.5, 1.0, 2.0, 4.0, 8.0],
-    "nf_rows": [1, 2, 4, 8, 16],
+    "nf_rows": [2, 4, 8, 16, 32],
     "nf_lds_kb": [0, 16, 32, 48, 64],
     "nf_block": [64, 128, 256],
 }
@@ -61,6 +62,15 @@ def cached_tuning(arch=None, path=DEFAULT_CACHE):
     if cache.get("arch", "").split(":")[0] != arch.split(":")[0]:
         return None
     return cache["tuning"]
+
+
+def cache_is_current(path=DEFAULT_CACHE):
+    """True when the cache was tuned on the current kernel source and build
+    flags (its `kernels_sha256` equals bench.kernels_digest())."""
+    if not os.path.exists(path):
+        return False
+    import bench
+    return json.load(open(path)).get("kernels_sha256") == bench.kernels_digest()
 
 
 def cached_serve_tuning(arch=None, path=DEFAULT_CACHE):
@@ -212,8 +222,8 @@ def main():
     out = tr.output(hits)
     best, ms, trials = tune(tr, hits, out, log=log)
     arch = torch.cuda.get_device_properties(0).gcnArchName
-    res = {"arch": arch, "workload": desc, "n_hits": hits.n_hits, "best_ms": ms, "tuning": best,
-           "trials": [{"tuning": t, "ms": m} for t, m in trials]}
+    res = {"arch": arch, "kernels_sha256": bench.kernels_digest(), "workload": desc, "n_hits": hits.n_hits,
+           "best_ms": ms, "tuning": best, "trials": [{"tuning": t, "ms": m} for t, m in trials]}
     if os.path.exists(args.out):  # keep the serving result of an earlier run
         prev = json.load(open(args.out))
         if "serve" in prev and prev.get("arch", "").split(":")[0] == arch.split(":")[0]:

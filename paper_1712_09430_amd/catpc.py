@@ -22,7 +22,7 @@ FLAG_VALID, FLAG_STOP_SINPHI, FLAG_STOP_ARC, FLAG_SPD_FAIL, FLAG_REFIT64 = 1, 2,
 N_STAGES = 8
 STAGES = ("row_index", "grid", "neighbours", "clean_start", "scan", "compact", "tracklets", "refit64")
 
-EXPORTS = ("catpc_stage_times", "catpc_work_counts", "catpc_default_params", "catpc_default_tuning", "catpc_row_stride", "catpc_workspace_bytes", "catpc_create", "catpc_destroy",
+EXPORTS = ("catpc_sector_frame", "catpc_to_global", "catpc_stage_times", "catpc_work_counts", "catpc_default_params", "catpc_default_tuning", "catpc_row_stride", "catpc_workspace_bytes", "catpc_create", "catpc_destroy",
            "catpc_set_params", "catpc_set_tuning", "catpc_get_tuning", "catpc_track_batch", "catpc_track_plain",
            "catpc_result", "catpc_fetch_tracklets", "catpc_select_tracklets", "catpc_select_result", "catpc_refit_tracks", "catpc_default_merge_params", "catpc_merge_tracks", "catpc_merge_counts", "catpc_fp32_probe", "catpc_probe_copy", "catpc_probe_fma",
            "catpc_last_error")
@@ -39,6 +39,10 @@ class catpc_params(ctypes.Structure):
                 ("nf_win_y", ctypes.c_float), ("nf_win_z", ctypes.c_float), ("nf_chi2_max", ctypes.c_float),
                 ("tc_gate_nsigma", ctypes.c_float), ("tc_max_miss", ctypes.c_int32), ("min_hits", ctypes.c_int32),
                 ("precision", ctypes.c_int32)]
+
+
+class catpc_geometry(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int32), ("row_x", ctypes.c_void_p), ("sectors_per_side", ctypes.c_int32)]
 
 
 class catpc_tuning(ctypes.Structure):
@@ -102,7 +106,11 @@ def lib():
         L.catpc_row_stride.restype = ctypes.c_int32
         L.catpc_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]
         L.catpc_workspace_bytes.restype = ctypes.c_size_t
-        L.catpc_create.argtypes = [ctypes.c_int32, _vp, P(catpc_params), ctypes.c_int64, ctypes.c_int32, P(_vp)]
+        L.catpc_create.argtypes = [P(catpc_geometry), P(catpc_params), ctypes.c_int64, ctypes.c_int32, P(_vp)]
+        L.catpc_sector_frame.argtypes = [P(catpc_geometry), ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int32)]
+        L.catpc_sector_frame.restype = st
+        L.catpc_to_global.argtypes = [P(catpc_geometry), ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp]
+        L.catpc_to_global.restype = st
         L.catpc_create.restype = st
         L.catpc_destroy.argtypes = [_vp]
         L.catpc_destroy.restype = None
@@ -184,12 +192,38 @@ def catpc_workspace_bytes(n_rows, max_hits, max_sectors):
     return int(lib().catpc_workspace_bytes(n_rows, max_hits, max_sectors))
 
 
-def catpc_create(row_x, params, max_hits, max_sectors):
+def catpc_geometry_of(row_x, sectors_per_side=18):
+    """A catpc_geometry for row_x (the array is kept on the returned struct)."""
     rx = np.ascontiguousarray(row_x, np.float32)
+    g = catpc_geometry(len(rx), rx.ctypes.data, int(sectors_per_side))
+    g._rx = rx
+    return g
+
+
+def catpc_create(row_x, params, max_hits, max_sectors, sectors_per_side=18):
+    g = catpc_geometry_of(row_x, sectors_per_side)
     h = _vp()
-    _check(lib().catpc_create(len(rx), rx.ctypes.data, ctypes.byref(params), int(max_hits), int(max_sectors),
+    _check(lib().catpc_create(ctypes.byref(g), ctypes.byref(params), int(max_hits), int(max_sectors),
                               ctypes.byref(h)))
     return h
+
+
+def catpc_sector_frame(geom, sector_id):
+    """(alpha rad, side +1/-1) of a sector (host call)."""
+    a, sd = ctypes.c_double(), ctypes.c_int32()
+    _check(lib().catpc_sector_frame(ctypes.byref(geom), int(sector_id), ctypes.byref(a), ctypes.byref(sd)))
+    return a.value, sd.value
+
+
+def catpc_to_global(geom, sector_id, x, param):
+    """Sector-frame (x, y, z, sin phi, tan lambda, q/pT) -> global (X, Y, Z,
+    phi, tan lambda, q/pT), float64[n, 6] (host call)."""
+    xs = np.ascontiguousarray(x, np.float32)
+    ps = np.ascontiguousarray(param, np.float32).reshape(-1, 5)
+    out = np.empty((len(xs), 6), np.float64)
+    _check(lib().catpc_to_global(ctypes.byref(geom), int(sector_id), len(xs), xs.ctypes.data, ps.ctypes.data,
+                                 out.ctypes.data))
+    return out
 
 
 def catpc_destroy(ctx):

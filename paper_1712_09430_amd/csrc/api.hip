@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -37,12 +38,14 @@ catpc_status hip_fail(hipError_t e, const char* what) {
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t row_first, hdr, bins, sorted, raw_up, raw_dn, mask, blk_sec, blk_cnt, blk_off, grp_off, start_glob, chain,
+  size_t row_first, hdr, bins, sorted, raw_up, raw_dn, mask, blk_sec, blk_cnt, blk_off, grp_off, start_glob, start_sec, chain,
       owner, sel_cnt, sel_local, sel_loc, sel_grp, sel_mask, mrec, mkey_a, mkey_b, mpair, mover, mslot, mchunk, counters;
   size_t total;
 };
 
-Layout plan(int32_t R, int64_t H, int32_t S) {
+// Workspace layout; `hot_only` leaves out the arrays of the selection and the
+// merging (the stage chain of the batched form never touches them).
+Layout plan(int32_t R, int64_t H, int32_t S, bool hot_only = false) {
   Layout L;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t p = o; o += align_up(bytes); return p; };
@@ -59,13 +62,14 @@ Layout plan(int32_t R, int64_t H, int32_t S) {
   L.blk_off = take(sizeof(int64_t) * (nblk + 8));
   L.grp_off = take(sizeof(int64_t) * (nblk / 1024 + 8));
   L.start_glob = take(sizeof(int32_t) * (size_t)(H + 1));
+  L.start_sec = take(sizeof(int32_t) * (size_t)(H + 1));
   L.chain = take(sizeof(ChainHit) * (size_t)(H + 1));
-  const size_t slots = (size_t)(H / 3) + 2;  // tracklets <= H/3: seeds are disjoint chains of >= 3 hits
-  L.owner = take(sizeof(unsigned) * (size_t)(H + 1));
+  const size_t slots = hot_only ? 0 : (size_t)(H / 3) + 2;  // tracklets <= H/3: seeds are disjoint chains of >= 3 hits
+  L.owner = take(hot_only ? 0 : sizeof(unsigned) * (size_t)(H + 1));
   L.sel_cnt = take(sizeof(int32_t) * slots);
   L.sel_local = take(sizeof(int32_t) * slots);
   L.sel_loc = take(sizeof(int2) * slots);
-  L.sel_grp = take(sizeof(longlong2) * (slots / 1024 + 8));
+  L.sel_grp = take(hot_only ? 0 : sizeof(longlong2) * (slots / 1024 + 8));
   L.sel_mask = take(sizeof(uint16_t) * slots * (size_t)sel_chunks(R));
   L.mrec = take(sizeof(float4) * slots);
   L.mkey_a = take(sizeof(unsigned long long) * slots);
@@ -73,10 +77,44 @@ Layout plan(int32_t R, int64_t H, int32_t S) {
   L.mpair = take(sizeof(int2) * (size_t)kMergePairsPerSlot * slots);
   L.mover = take(sizeof(int32_t) * slots);
   L.mslot = take(sizeof(int32_t) * slots);
-  L.mchunk = take(sizeof(int32_t) * ((size_t)S + 1));
+  L.mchunk = take(hot_only ? 0 : sizeof(int32_t) * ((size_t)S + 1));
   L.counters = take(sizeof(unsigned long long) * kNumCounters);
   L.total = o;
   return L;
+}
+
+// The workspace arrays of layout L inside the device block b.
+Workspace carve(char* b, const Layout& L) {
+  Workspace w;
+  w.row_first = (int32_t*)(b + L.row_first);
+  w.hdr = (RowHdr*)(b + L.hdr);
+  w.bins = (int32_t*)(b + L.bins);
+  w.sorted = (SortedHit*)(b + L.sorted);
+  w.raw_up = (int32_t*)(b + L.raw_up);
+  w.raw_dn = (int32_t*)(b + L.raw_dn);
+  w.start_mask = (uint64_t*)(b + L.mask);
+  w.blk_sec = (int32_t*)(b + L.blk_sec);
+  w.blk_cnt = (int32_t*)(b + L.blk_cnt);
+  w.blk_off = (int64_t*)(b + L.blk_off);
+  w.grp_off = (int64_t*)(b + L.grp_off);
+  w.start_glob = (int32_t*)(b + L.start_glob);
+  w.start_sec = (int32_t*)(b + L.start_sec);
+  w.chain = (ChainHit*)(b + L.chain);
+  w.owner = (unsigned*)(b + L.owner);
+  w.sel_cnt = (int32_t*)(b + L.sel_cnt);
+  w.sel_local = (int32_t*)(b + L.sel_local);
+  w.sel_loc = (int2*)(b + L.sel_loc);
+  w.sel_grp = (longlong2*)(b + L.sel_grp);
+  w.sel_mask = (uint16_t*)(b + L.sel_mask);
+  w.mrec = (float4*)(b + L.mrec);
+  w.mkey_a = (unsigned long long*)(b + L.mkey_a);
+  w.mkey_b = (unsigned long long*)(b + L.mkey_b);
+  w.mpair = (int2*)(b + L.mpair);
+  w.mover = (int32_t*)(b + L.mover);
+  w.mslot = (int32_t*)(b + L.mslot);
+  w.mchunk = (int32_t*)(b + L.mchunk);
+  w.counters = (unsigned long long*)(b + L.counters);
+  return w;
 }
 
 // Arguments of the last captured batched chain; replay only if identical.
@@ -164,12 +202,30 @@ catpc_status check_params(const catpc_params* p) {
   return CATPC_OK;
 }
 
-catpc_status check_io(const catpc_ctx* ctx, const catpc_input* in, const catpc_output* out, bool need_host_off) {
-  if (!ctx) return fail(CATPC_E_INVALID, "ctx is NULL");
+catpc_status check_tuning(const catpc_tuning* t) {
+  if (!(t->bin_hits >= 0.25f && t->bin_hits <= 64.0f)) return fail(CATPC_E_INVALID, "bin_hits out of [0.25, 64]");
+  if (t->nf_block < 64 || t->nf_block > 256 || t->nf_block % 64)
+    return fail(CATPC_E_INVALID, "nf_block must be a multiple of 64 in [64, 256]");
+  if (t->tc_block < 64 || t->tc_block > 256 || t->tc_block % 64)
+    return fail(CATPC_E_INVALID, "tc_block must be a multiple of 64 in [64, 256]");
+  if (t->tc_waves_per_cu < 1 || t->tc_waves_per_cu > 32) return fail(CATPC_E_INVALID, "tc_waves_per_cu out of [1, 32]");
+  if (t->use_graph < 0 || t->use_graph > 1) return fail(CATPC_E_INVALID, "use_graph must be 0 or 1");
+  if (t->nf_rows < 1 || t->nf_rows > 32) return fail(CATPC_E_INVALID, "nf_rows out of [1, 32]");
+  if (t->nf_lds_kb < 0 || t->nf_lds_kb > 64) return fail(CATPC_E_INVALID, "nf_lds_kb out of [0, 64]");
+  if (t->tc_xcd < 0 || t->tc_xcd > 1) return fail(CATPC_E_INVALID, "tc_xcd must be 0 or 1");
+  if (t->tc_occupancy != 0 && t->tc_occupancy != 5 && t->tc_occupancy != 6 && t->tc_occupancy != 8)
+    return fail(CATPC_E_INVALID, "tc_occupancy must be 0, 5, 6 or 8");
+  if (t->tc_sync < 0 || t->tc_sync > 1) return fail(CATPC_E_INVALID, "tc_sync must be 0 or 1");
+  if (t->merge_pair_cap < 0) return fail(CATPC_E_INVALID, "merge_pair_cap must be >= 0");
+  return CATPC_OK;
+}
+
+catpc_status check_io_within(int64_t max_hits, int32_t max_sectors, const catpc_input* in, const catpc_output* out,
+                             bool need_host_off) {
   if (!in || !out) return fail(CATPC_E_INVALID, "input or output is NULL");
-  if (in->n_sectors < 0 || in->n_sectors > ctx->max_sectors)
+  if (in->n_sectors < 0 || in->n_sectors > max_sectors)
     return fail(CATPC_E_INVALID, "n_sectors out of [0, max_sectors]");
-  if (in->n_hits < 0 || in->n_hits > ctx->max_hits) return fail(CATPC_E_INVALID, "n_hits out of [0, max_hits]");
+  if (in->n_hits < 0 || in->n_hits > max_hits) return fail(CATPC_E_INVALID, "n_hits out of [0, max_hits]");
   if (in->n_sectors == 0) return CATPC_OK;
   if (!in->hit_offset) return fail(CATPC_E_INVALID, "hit_offset is NULL");
   if (in->n_hits > 0 && (!in->y || !in->z || !in->row)) return fail(CATPC_E_INVALID, "hit arrays are NULL");
@@ -196,6 +252,11 @@ catpc_status check_io(const catpc_ctx* ctx, const catpc_input* in, const catpc_o
   return CATPC_OK;
 }
 
+catpc_status check_io(const catpc_ctx* ctx, const catpc_input* in, const catpc_output* out, bool need_host_off) {
+  if (!ctx) return fail(CATPC_E_INVALID, "ctx is NULL");
+  return check_io_within(ctx->max_hits, ctx->max_sectors, in, out, need_host_off);
+}
+
 Inputs inputs_of(const catpc_input* in) {
   Inputs I;
   I.x = in->x;
@@ -220,33 +281,60 @@ TrackletOut tracklets_of(const catpc_output* out) {
   return T;
 }
 
+// What the stage chain needs: the pad-row geometry on the device, method
+// constants, launch shape and workspace -- from a context, or from the fixed
+// device array of the no-allocation entry point.
+struct Chain {
+  int32_t n_rows = 0;
+  const float* row_x = nullptr;  // device [n_rows]
+  const float4* rowk = nullptr;  // device [n_rows]
+  Consts consts{};
+  int32_t precision = 0;
+  catpc_tuning tuning{};
+  int n_cu = 256;
+  Workspace ws{};
+};
+
+Chain chain_of(const catpc_ctx* ctx) {
+  Chain c;
+  c.n_rows = ctx->n_rows;
+  c.row_x = ctx->row_x;
+  c.rowk = ctx->rowk;
+  c.consts = ctx->consts;
+  c.precision = ctx->params.precision;
+  c.tuning = ctx->tuning;
+  c.n_cu = ctx->n_cu;
+  c.ws = ctx->ws;
+  return c;
+}
+
 // Persistent grid of the tracklet kernel; `max_tracklets` (if >= 0) bounds
 // the useful number of waves (a seed has at least three hits).
-int tc_grid(const catpc_ctx* ctx, int64_t max_tracklets = -1) {
-  int64_t waves = (int64_t)ctx->n_cu * (ctx->tuning.tc_waves_per_cu > 0 ? ctx->tuning.tc_waves_per_cu : 8);
+int tc_grid(const Chain& c, int64_t max_tracklets = -1) {
+  int64_t waves = (int64_t)c.n_cu * (c.tuning.tc_waves_per_cu > 0 ? c.tuning.tc_waves_per_cu : 8);
   if (max_tracklets >= 0) waves = std::min<int64_t>(waves, std::max<int64_t>(1, (max_tracklets + 63) / 64));
-  const int64_t wpb = ctx->tuning.tc_block / 64;
+  const int64_t wpb = c.tuning.tc_block / 64;
   return (int)((waves + wpb - 1) / wpb);
 }
 
 // The stage chain for sectors [s0, s1) with hits [h0, h1).  With `ev`
 // (CATPC_N_STAGES + 1 events) an event is recorded before each stage and after
 // the last one.
-catpc_status enqueue_span(catpc_ctx* ctx, const catpc_input* in, const catpc_output* out, Span sp, hipStream_t st,
+catpc_status enqueue_span(const Chain& c, const catpc_input* in, const catpc_output* out, Span sp, hipStream_t st,
                           hipEvent_t* ev = nullptr) {
   const Inputs I = inputs_of(in);
-  const Workspace& ws = ctx->ws;
+  const Workspace& ws = c.ws;
   int32_t* up = out->nf_up ? out->nf_up : ws.raw_up;
   int32_t* dn = out->nf_dn ? out->nf_dn : ws.raw_dn;
-  const int nb = ctx->tuning.nf_block;
+  const int nb = c.tuning.nf_block;
   auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev[k], st) : hipSuccess; };
   HIP_TRY(mark(0));
-  HIP_TRY(launch_row_index(I, sp, ctx->n_rows, ctx->row_x, ws, nb, st));
+  HIP_TRY(launch_row_index(I, sp, c.n_rows, c.row_x, ws, nb, st));
   HIP_TRY(mark(1));
-  HIP_TRY(launch_grid(I, sp, ctx->n_rows, ctx->tuning.bin_hits, ws, st));
+  HIP_TRY(launch_grid(I, sp, c.n_rows, c.tuning.bin_hits, ws, st));
   HIP_TRY(mark(2));
-  HIP_TRY(launch_neighbours(I, sp, ctx->n_rows, ctx->rowk, ctx->consts, ws, up, dn, nb, ctx->tuning.nf_rows,
-                            ctx->tuning.nf_lds_kb * 1024, st));
+  HIP_TRY(launch_neighbours(I, sp, c.n_rows, c.rowk, c.consts, ws, up, dn, nb, c.tuning.nf_rows,
+                            c.tuning.nf_lds_kb * 1024, st));
   HIP_TRY(mark(3));
   HIP_TRY(launch_clean_start(I, sp, up, dn, out->link_up, out->link_dn, ws, st));
   HIP_TRY(mark(4));
@@ -255,30 +343,30 @@ catpc_status enqueue_span(catpc_ctx* ctx, const catpc_input* in, const catpc_out
   HIP_TRY(launch_compact(I, sp, out->tracklet_offset, out->start_hit, ws, st));
   HIP_TRY(mark(6));
   if (out->tracklet_capacity > 0) {
-    HIP_TRY(launch_tracklets(I, sp, ctx->n_rows, ctx->row_x, ctx->consts, ws, out->tracklet_offset, 0,
-                             out->tracklet_capacity, tracklets_of(out), tc_grid(ctx, (sp.h1 - sp.h0) / 3 + 1),
-                             ctx->tuning.tc_block, ctx->tuning.tc_xcd ? kXcds : 1,
-                             ctx->tuning.tc_occupancy, ctx->tuning.tc_sync, st));
+    HIP_TRY(launch_tracklets(I, sp, c.n_rows, c.row_x, c.consts, ws, out->tracklet_offset, 0,
+                             out->tracklet_capacity, tracklets_of(out), tc_grid(c, (sp.h1 - sp.h0) / 3 + 1),
+                             c.tuning.tc_block, c.tuning.tc_xcd ? kXcds : 1, c.tuning.tc_occupancy,
+                             c.tuning.tc_sync, st));
   }
   HIP_TRY(mark(7));
   return CATPC_OK;
 }
 
-catpc_status enqueue_refit(catpc_ctx* ctx, const catpc_input* in, const catpc_output* out, Span sp, int64_t first,
+catpc_status enqueue_refit(const Chain& c, const catpc_input* in, const catpc_output* out, Span sp, int64_t first,
                            hipStream_t st) {
-  if (ctx->params.precision == 0 || out->tracklet_capacity == 0) return CATPC_OK;
-  HIP_TRY(launch_refit64(inputs_of(in), sp, ctx->n_rows, ctx->row_x, ctx->consts, ctx->ws, out->tracklet_offset,
-                         first, out->tracklet_capacity, tracklets_of(out), ctx->n_cu * 4, st));
+  if (c.precision == 0 || out->tracklet_capacity == 0) return CATPC_OK;
+  HIP_TRY(launch_refit64(inputs_of(in), sp, c.n_rows, c.row_x, c.consts, c.ws, out->tracklet_offset, first,
+                         out->tracklet_capacity, tracklets_of(out), c.n_cu * 4, st));
   return CATPC_OK;
 }
 
-catpc_status enqueue_batch(catpc_ctx* ctx, const catpc_input* in, const catpc_output* out, hipStream_t st) {
-  HIP_TRY(launch_reset(ctx->ws.counters, kNumCounters, st));
+catpc_status enqueue_batch(const Chain& c, const catpc_input* in, const catpc_output* out, hipStream_t st) {
+  HIP_TRY(launch_reset(c.ws.counters, kNumCounters, st));
   if (in->n_sectors == 0) return CATPC_OK;
   Span sp{0, in->n_sectors, 0, in->n_hits};
-  catpc_status rc = enqueue_span(ctx, in, out, sp, st);
+  catpc_status rc = enqueue_span(c, in, out, sp, st);
   if (rc) return rc;
-  return enqueue_refit(ctx, in, out, sp, 0, st);
+  return enqueue_refit(c, in, out, sp, 0, st);
 }
 
 void drop_graph(catpc_ctx* ctx) {
@@ -390,14 +478,74 @@ size_t catpc_workspace_bytes(int32_t n_rows, int64_t max_hits, int32_t max_secto
 
 const char* catpc_last_error(void) { return g_err.c_str(); }
 
-catpc_status catpc_create(int32_t n_rows, const float* row_x, const catpc_params* params, int64_t max_hits,
+namespace {
+
+catpc_status check_geometry(const catpc_geometry* g) {
+  if (!g) return fail(CATPC_E_INVALID, "geometry is NULL");
+  if (g->n_rows < 3 || g->n_rows > kMaxRows || !g->row_x)
+    return fail(CATPC_E_INVALID, "need 3 <= n_rows <= 4096 and row_x");
+  for (int32_t r = 0; r < g->n_rows; ++r)
+    if (!(g->row_x[r] > 0.0f) || (r > 0 && !(g->row_x[r] > g->row_x[r - 1])))
+      return fail(CATPC_E_INVALID, "row_x must be positive and strictly ascending");
+  if (g->sectors_per_side < 0) return fail(CATPC_E_INVALID, "sectors_per_side must be >= 0");
+  return CATPC_OK;
+}
+
+int sectors_per_side(const catpc_geometry* g) { return g->sectors_per_side > 0 ? g->sectors_per_side : 18; }
+
+}  // namespace
+
+catpc_status catpc_sector_frame(const catpc_geometry* geom, int32_t sector_id, double* alpha, int32_t* side) {
+  if (!geom || !alpha || !side) return fail(CATPC_E_INVALID, "NULL argument");
+  if (geom->sectors_per_side < 0) return fail(CATPC_E_INVALID, "sectors_per_side must be >= 0");
+  const int n = sectors_per_side(geom);
+  if (sector_id < 0 || sector_id >= 2 * n) return fail(CATPC_E_INVALID, "sector id out of range");
+  const double pi = 3.14159265358979323846;
+  *alpha = ((double)(sector_id % n) + 0.5) * (2.0 * pi / (double)n);
+  *side = sector_id < n ? 1 : -1;
+  return CATPC_OK;
+}
+
+catpc_status catpc_to_global(const catpc_geometry* geom, int32_t sector_id, int64_t n, const float* x,
+                             const float* param, double* out) {
+  double alpha = 0.0;
+  int32_t side = 0;
+  catpc_status rc = catpc_sector_frame(geom, sector_id, &alpha, &side);
+  if (rc) return rc;
+  if (n < 0 || (n > 0 && (!x || !param || !out))) return fail(CATPC_E_INVALID, "NULL array or n < 0");
+  const double pi = 3.14159265358979323846;
+  const double ca = std::cos(alpha), sa = std::sin(alpha);
+  bool bad = false;
+  for (int64_t i = 0; i < n; ++i) {
+    const float* p = param + 5 * i;
+    double* o = out + 6 * i;
+    const double lx = x[i], ly = p[0], sp = p[2];
+    o[0] = lx * ca - ly * sa;
+    o[1] = lx * sa + ly * ca;
+    o[2] = p[1];
+    if (!(std::fabs(sp) <= 1.0)) {
+      o[3] = std::nan("");
+      bad = true;
+    } else {
+      double phi = std::asin(sp) + alpha;
+      while (phi > pi) phi -= 2.0 * pi;
+      while (phi <= -pi) phi += 2.0 * pi;
+      o[3] = phi;
+    }
+    o[4] = p[3];
+    o[5] = p[4];
+  }
+  return bad ? fail(CATPC_E_INVALID, "|sin phi| > 1 in an entry (its phi is NaN)") : CATPC_OK;
+}
+
+catpc_status catpc_create(const catpc_geometry* geom, const catpc_params* params, int64_t max_hits,
                           int32_t max_sectors, catpc_ctx** out) {
   if (!out) return fail(CATPC_E_INVALID, "out is NULL");
   *out = nullptr;
-  if (n_rows < 3 || n_rows > kMaxRows || !row_x) return fail(CATPC_E_INVALID, "need 3 <= n_rows <= 4096 and row_x");
-  for (int32_t r = 0; r < n_rows; ++r)
-    if (!(row_x[r] > 0.0f) || (r > 0 && !(row_x[r] > row_x[r - 1])))
-      return fail(CATPC_E_INVALID, "row_x must be positive and strictly ascending");
+  catpc_status grc = check_geometry(geom);
+  if (grc) return grc;
+  const int32_t n_rows = geom->n_rows;
+  const float* row_x = geom->row_x;
   if (max_hits < 0 || max_hits >= (int64_t)1 << 31) return fail(CATPC_E_INVALID, "max_hits out of [0, 2^31)");
   if (max_sectors < 0 || max_hits + (int64_t)max_sectors * n_rows >= (int64_t)1 << 31)
     return fail(CATPC_E_INVALID, "max_hits + max_sectors * n_rows must stay below 2^31");
@@ -441,35 +589,8 @@ catpc_status catpc_create(int32_t n_rows, const float* row_x, const catpc_params
     if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->host_total, sizeof(int64_t), 0);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
     if (e == hipSuccess) {
-      char* b = (char*)ctx->ws_mem;
+      ctx->ws = carve((char*)ctx->ws_mem, L);
       Workspace& w = ctx->ws;
-      w.row_first = (int32_t*)(b + L.row_first);
-      w.hdr = (RowHdr*)(b + L.hdr);
-      w.bins = (int32_t*)(b + L.bins);
-      w.sorted = (SortedHit*)(b + L.sorted);
-      w.raw_up = (int32_t*)(b + L.raw_up);
-      w.raw_dn = (int32_t*)(b + L.raw_dn);
-      w.start_mask = (uint64_t*)(b + L.mask);
-      w.blk_sec = (int32_t*)(b + L.blk_sec);
-      w.blk_cnt = (int32_t*)(b + L.blk_cnt);
-      w.blk_off = (int64_t*)(b + L.blk_off);
-      w.grp_off = (int64_t*)(b + L.grp_off);
-      w.start_glob = (int32_t*)(b + L.start_glob);
-      w.chain = (ChainHit*)(b + L.chain);
-      w.owner = (unsigned*)(b + L.owner);
-      w.sel_cnt = (int32_t*)(b + L.sel_cnt);
-      w.sel_local = (int32_t*)(b + L.sel_local);
-      w.sel_loc = (int2*)(b + L.sel_loc);
-      w.sel_grp = (longlong2*)(b + L.sel_grp);
-      w.sel_mask = (uint16_t*)(b + L.sel_mask);
-      w.mrec = (float4*)(b + L.mrec);
-      w.mkey_a = (unsigned long long*)(b + L.mkey_a);
-      w.mkey_b = (unsigned long long*)(b + L.mkey_b);
-      w.mpair = (int2*)(b + L.mpair);
-      w.mover = (int32_t*)(b + L.mover);
-      w.mslot = (int32_t*)(b + L.mslot);
-      w.mchunk = (int32_t*)(b + L.mchunk);
-      w.counters = (unsigned long long*)(b + L.counters);
       e = hipMemset(w.counters, 0, sizeof(unsigned long long) * kNumCounters);
     }
   }
@@ -504,20 +625,8 @@ catpc_status catpc_set_params(catpc_ctx* ctx, const catpc_params* params) {
 
 catpc_status catpc_set_tuning(catpc_ctx* ctx, const catpc_tuning* t) {
   if (!ctx || !t) return fail(CATPC_E_INVALID, "ctx or tuning is NULL");
-  if (!(t->bin_hits >= 0.25f && t->bin_hits <= 64.0f)) return fail(CATPC_E_INVALID, "bin_hits out of [0.25, 64]");
-  if (t->nf_block < 64 || t->nf_block > 256 || t->nf_block % 64)
-    return fail(CATPC_E_INVALID, "nf_block must be a multiple of 64 in [64, 256]");
-  if (t->tc_block < 64 || t->tc_block > 256 || t->tc_block % 64)
-    return fail(CATPC_E_INVALID, "tc_block must be a multiple of 64 in [64, 256]");
-  if (t->tc_waves_per_cu < 1 || t->tc_waves_per_cu > 32) return fail(CATPC_E_INVALID, "tc_waves_per_cu out of [1, 32]");
-  if (t->use_graph < 0 || t->use_graph > 1) return fail(CATPC_E_INVALID, "use_graph must be 0 or 1");
-  if (t->nf_rows < 1 || t->nf_rows > 32) return fail(CATPC_E_INVALID, "nf_rows out of [1, 32]");
-  if (t->nf_lds_kb < 0 || t->nf_lds_kb > 64) return fail(CATPC_E_INVALID, "nf_lds_kb out of [0, 64]");
-  if (t->tc_xcd < 0 || t->tc_xcd > 1) return fail(CATPC_E_INVALID, "tc_xcd must be 0 or 1");
-  if (t->tc_occupancy != 0 && t->tc_occupancy != 5 && t->tc_occupancy != 6 && t->tc_occupancy != 8)
-    return fail(CATPC_E_INVALID, "tc_occupancy must be 0, 5, 6 or 8");
-  if (t->tc_sync < 0 || t->tc_sync > 1) return fail(CATPC_E_INVALID, "tc_sync must be 0 or 1");
-  if (t->merge_pair_cap < 0) return fail(CATPC_E_INVALID, "merge_pair_cap must be >= 0");
+  catpc_status rc = check_tuning(t);
+  if (rc) return rc;
   ctx->tuning = *t;
   return CATPC_OK;
 }
@@ -549,10 +658,10 @@ catpc_status catpc_track_batch(catpc_ctx* ctx, const catpc_input* in, const catp
     k.params = ctx->params;
     k.tuning = ctx->tuning;
     rc = replay(ctx, ctx->have_graph, ctx->key, ctx->graph, ctx->exec, k,
-                [&](hipStream_t cs) { return enqueue_batch(ctx, in, out, cs); }, st);
+                [&](hipStream_t cs) { return enqueue_batch(chain_of(ctx), in, out, cs); }, st);
     if (rc) return rc;
   } else {
-    rc = enqueue_batch(ctx, in, out, st);
+    rc = enqueue_batch(chain_of(ctx), in, out, st);
     if (rc) return rc;
   }
   ctx->last_in = *in;
@@ -573,11 +682,11 @@ catpc_status catpc_track_plain(catpc_ctx* ctx, const catpc_input* in, const catp
   const int64_t* h = in->hit_offset_host;
   for (int32_t s = 0; s < in->n_sectors; ++s) {
     Span sp{s, s + 1, h[s], h[s + 1]};
-    rc = enqueue_span(ctx, in, out, sp, st);
+    rc = enqueue_span(chain_of(ctx), in, out, sp, st);
     if (rc) return rc;
   }
   if (in->n_sectors > 0) {
-    rc = enqueue_refit(ctx, in, out, Span{0, in->n_sectors, 0, in->n_hits}, 0, st);
+    rc = enqueue_refit(chain_of(ctx), in, out, Span{0, in->n_sectors, 0, in->n_hits}, 0, st);
     if (rc) return rc;
   }
   ctx->last_in = *in;
@@ -632,10 +741,10 @@ catpc_status catpc_fetch_tracklets(catpc_ctx* ctx, const catpc_input* in, int64_
   o.tracklet_offset = ctx->last_out.tracklet_offset;
   HIP_TRY(launch_reset(ctx->ws.counters, kXcds, st));
   HIP_TRY(launch_tracklets(I, sp, ctx->n_rows, ctx->row_x, ctx->consts, ctx->ws, o.tracklet_offset, first,
-                           o.tracklet_capacity, tracklets_of(&o), tc_grid(ctx), ctx->tuning.tc_block,
+                           o.tracklet_capacity, tracklets_of(&o), tc_grid(chain_of(ctx)), ctx->tuning.tc_block,
                            ctx->tuning.tc_xcd ? kXcds : 1, ctx->tuning.tc_occupancy,
                            ctx->tuning.tc_sync, st));
-  return enqueue_refit(ctx, in, &o, sp, first, st);
+  return enqueue_refit(chain_of(ctx), in, &o, sp, first, st);
 }
 
 catpc_status catpc_stage_times(catpc_ctx* ctx, const catpc_input* in, const catpc_output* out, void* stream,
@@ -652,8 +761,8 @@ catpc_status catpc_stage_times(catpc_ctx* ctx, const catpc_input* in, const catp
   HIP_TRY(launch_reset(ctx->ws.counters, kNumCounters, st));
   const Span sp{0, in->n_sectors, 0, in->n_hits};
   if (in->n_sectors > 0) {
-    rc = enqueue_span(ctx, in, out, sp, st, ev);
-    if (!rc) rc = enqueue_refit(ctx, in, out, sp, 0, st);
+    rc = enqueue_span(chain_of(ctx), in, out, sp, st, ev);
+    if (!rc) rc = enqueue_refit(chain_of(ctx), in, out, sp, 0, st);
   } else {
     for (int k = 0; k < CATPC_N_STAGES; ++k) HIP_TRY(hipEventRecord(ev[k], st));
   }

@@ -70,6 +70,7 @@ __global__ void k_reset(unsigned long long* c, int n) {
   if ((int)threadIdx.x < n) c[threadIdx.x] = 0ull;
 }
 
+
 // --------------------------------------------------------------- row index
 // Blocks [0, item_blocks): one thread per (sector, row 0..R) item, first hit
 // of the row by binary search (monotone in r for any input; row 0 starts at
@@ -492,6 +493,126 @@ __global__ __launch_bounds__(256) void k_neighbours(Inputs in, Span sp, int R, c
     nf_hits<false>(ws.sorted + a + rf[c0], n, a, s, R, rowk, c, ws, S, out_up, out_dn);
 }
 
+// Renumbering of a launch's workgroups so that each die (workgroups are dealt
+// out round-robin over the kXcds dies) takes one contiguous run of them: the
+// neighbour rows that consecutive workgroups share stay in one die's L2.
+__device__ __forceinline__ int64_t die_contiguous(int64_t b, int64_t nblk) {
+  const int64_t x = b % kXcds, k = b / kXcds;
+  const int64_t q = nblk / kXcds, rem = nblk % kXcds;
+  return x * q + min(x, rem) + k;
+}
+
+// The hits of a window in one row of a bin grid: the ranges of its first two
+// z rows of bins (loaded together), and the bounds of any further z row.
+// Bin b of the row (b = z * ny + y) spans positions [cs[base + b],
+// cs[base + b + 1]).
+struct NfWin {
+  int p0, n0, p1, n1;
+  int y0, y1, z2, z1, base, ny;
+};
+
+__device__ __forceinline__ NfWin nf_window(const int32_t* cs, int base, float ymin, float iby, int ny, float zmin,
+                                           float ibz, int nz, float yc, float wy, float zc, float wz) {
+  NfWin w;
+  w.y0 = bin_of((yc - wy) - kBinMargin, ymin, iby, ny);
+  w.y1 = bin_of((yc + wy) + kBinMargin, ymin, iby, ny);
+  const int z0 = bin_of((zc - wz) - kBinMargin, zmin, ibz, nz);
+  w.z1 = bin_of((zc + wz) + kBinMargin, zmin, ibz, nz);
+  w.base = base;
+  w.ny = ny;
+  const int r0 = w.base + z0 * ny;
+  const int r1 = w.base + min(z0 + 1, w.z1) * ny;
+  w.p0 = cs[r0 + w.y0];
+  w.n0 = cs[r0 + w.y1 + 1] - w.p0;
+  w.p1 = cs[r1 + w.y0];
+  w.n1 = z0 < w.z1 ? cs[r1 + w.y1 + 1] - w.p1 : 0;
+  w.z2 = z0 + 2;
+  return w;
+}
+
+// f(position) for every hit position of the window: the first two z rows as
+// one flat loop (lanes whose windows differ only in how the hits split over
+// the two rows run the same number of iterations), then any further z row.
+template <class F>
+__device__ __forceinline__ void nf_for(const NfWin& w, const int32_t* cs, F&& f) {
+  const int n = w.n0 + w.n1;
+  for (int k = 0; k < n; ++k) f(k < w.n0 ? w.p0 + k : w.p1 + (k - w.n0));
+  for (int iz = w.z2; iz <= w.z1; ++iz) {
+    const int rr = w.base + iz * w.ny;
+    const int e = cs[rr + w.y1 + 1];
+    for (int p = cs[rr + w.y0]; p < e; ++p) f(p);
+  }
+}
+
+// Keep the lexicographic minimum of (chi2, j, k) among pairs within the cut.
+__device__ __forceinline__ void nf_keep(float chi2, float chi2max, int32_t j, int32_t k, float& best, int32_t& bj,
+                                        int32_t& bk) {
+  if (!(chi2 <= chi2max)) return;
+  if (bj < 0 || chi2 < best || (chi2 == best && (j < bj || (j == bj && k < bk)))) {
+    best = chi2;
+    bj = j;
+    bk = k;
+  }
+}
+
+// Neighbour finder, in place.  One thread per hit in the order of the
+// grid-sorted array (sector, pad row, bin), so the lanes of a wave take hits
+// of one row and of the same or adjacent bins: their windows, and the number
+// of candidates they visit, are alike.  For the hit in row r the down
+// candidates (row r-1) and up candidates (row r+1) are the hits of the bins
+// the +-wy x +-wz windows around the ray predictions y x_{r+-1}/x_r,
+// z x_{r+-1}/x_r touch; every up candidate inside its window is paired with
+// every down candidate inside its window, re-read from memory (no per-lane
+// candidate list, so the kernel stays small enough for many resident waves).
+// Workgroups are renumbered die-contiguously.  rowk[r] = (x_{r+1}/x_r,
+// x_{r-1}/x_r, (x_r - x_{r-1}) / (x_{r+1} - x_{r-1})), each one binary32
+// division.
+__global__ __launch_bounds__(256) void k_nf_flat(Inputs in, Span sp, int R, const float4* __restrict__ rowk,
+                                                 Consts c, Workspace ws, int32_t* __restrict__ out_up,
+                                                 int32_t* __restrict__ out_dn, int64_t nblk) {
+  const int64_t L = die_contiguous(blockIdx.x, nblk);
+  const int64_t i = sp.h0 + L * blockDim.x + threadIdx.x;
+  if (i >= sp.h1) return;
+  const int64_t kb = (i - sp.h0) / kHitsPerBlock;
+  const int s = sector_from(in.hit_offset, sp.s1, ws.blk_sec[kb], i);
+  const SortedHit me = ws.sorted[i];
+  const int r = me.row;
+  const int64_t gr = (int64_t)s * R + r;
+  int32_t bj = -1, bk = -1;
+  if (r >= 1 && r <= R - 2) {
+    const RowHdr hu = ws.hdr[gr + 1], hd = ws.hdr[gr - 1];
+    if (hu.ny > 0 && hd.ny > 0) {
+      const float4 f = rowk[r];
+      const float fu = f.x, fd = f.y, t = f.z;
+      const float yi = me.y, zi = me.z;
+      const float yu = yi * fu, zu = zi * fu;
+      const float yd = yi * fd, zd = zi * fd;
+      const int32_t* bu = ws.bins + 2 * (int64_t)hu.bin_half;
+      const int32_t* bd = ws.bins + 2 * (int64_t)hd.bin_half;
+      const SortedHit* su = ws.sorted + hu.hit_base;
+      const SortedHit* sd = ws.sorted + hd.hit_base;
+      const NfWin wu = nf_window(bu, 0, hu.ymin, hu.iby, hu.ny, hu.zmin, hu.ibz, hu.nz, yu, c.wy, zu, c.wz);
+      const NfWin wd = nf_window(bd, 0, hd.ymin, hd.iby, hd.ny, hd.zmin, hd.ibz, hd.nz, yd, c.wy, zd, c.wz);
+      float best = 0.0f;
+      nf_for(wu, bu, [&](int pj) {
+        const float4 hj = *reinterpret_cast<const float4*>(su + pj);
+        if (!(fabsf(hj.x - yu) <= c.wy && fabsf(hj.y - zu) <= c.wz)) return;
+        const int32_t j = __float_as_int(hj.z);
+        nf_for(wd, bd, [&](int pk) {
+          const float4 hk = *reinterpret_cast<const float4*>(sd + pk);
+          if (!(fabsf(hk.x - yd) <= c.wy && fabsf(hk.y - zd) <= c.wz)) return;
+          const float ey = yi - (hk.x + t * (hj.x - hk.x));
+          const float ez = zi - (hk.y + t * (hj.y - hk.y));
+          nf_keep(ey * ey + ez * ez, c.chi2, j, __float_as_int(hk.z), best, bj, bk);
+        });
+      });
+    }
+  }
+  const int64_t o = in.hit_offset[s] + me.idx;
+  out_up[o] = bj;
+  out_dn[o] = bk;
+}
+
 // -------------------------------------------------------------- clean/start
 // One workgroup per kCleanRounds consecutive blocks of kHitsPerBlock hits:
 // each thread takes one hit of every block, issuing the loads of all its hits
@@ -655,6 +776,7 @@ __global__ __launch_bounds__(kHitsPerBlock) void k_compact(Inputs in, Span sp, i
         while (s + 1 < sp.s1 && in.hit_offset[s + 1] <= i) ++s;
         start_hit[pos] = (int32_t)(i - in.hit_offset[s]);
         ws.start_glob[pos] = (int32_t)i;
+        ws.start_sec[pos] = s;
         ++pos;
         m &= m - 1ull;
       } while (m);
@@ -977,12 +1099,13 @@ template <bool kSync>
 __device__ __forceinline__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __restrict__ row_x, const Consts& c,
                                const Workspace& ws, const int64_t* toff, int64_t slot, int64_t o,
                                const TrackletOut& out, int RS, int32_t* chunk_lds, Work& w) {
-  const int s = sector_of(toff, sp.s0, sp.s1, slot);
+  const int s = ws.start_sec[slot];
   const int64_t a = in.hit_offset[s];
   const int64_t gi = ws.start_glob[slot];
   const int32_t h0 = (int32_t)(gi - a);
   const int r0 = in.row[gi];
   int32_t* rec = out.row_hit + o * RS;
+  (void)toff;
   if (r0 < 1 || r0 > R - 3) {
     // A start hit has an unlinked hit row below it and two linked rows above
     // it, so on valid input it lies in rows 1 .. R-3.  Only a row value outside
@@ -2244,10 +2367,17 @@ hipError_t launch_grid(const Inputs& in, Span sp, int n_rows, float bin_hits, co
 hipError_t launch_neighbours(const Inputs& in, Span sp, int n_rows, const float4* rowk, const Consts& c,
                              const Workspace& ws, int32_t* up, int32_t* dn, int block, int rows, int lds_bytes,
                              hipStream_t st) {
+  const int64_t n = sp.h1 - sp.h0;
+  if (n == 0) return hipSuccess;
+  const int64_t flat_blocks = blocks_for(n, block);
+  if (lds_bytes <= 0) {
+    hipLaunchKernelGGL(k_nf_flat, dim3((unsigned)flat_blocks), dim3(block), 0, st, in, sp, n_rows, rowk, c, ws, up,
+                       dn, flat_blocks);
+    return hipGetLastError();
+  }
   rows = std::max(1, std::min(rows, kNfMaxRows));  // the workgroup stages the headers of rows + 2 rows
   const int64_t chunks = (n_rows + rows - 1) / rows;
   const int64_t items = (int64_t)(sp.s1 - sp.s0) * chunks;
-  if (sp.h1 - sp.h0 == 0 || items == 0) return hipSuccess;
   hipLaunchKernelGGL(k_neighbours, dim3((unsigned)items), dim3(block), (size_t)lds_bytes, st, in, sp, n_rows, rowk,
                      c, ws, up, dn, rows, lds_bytes);
   return hipGetLastError();

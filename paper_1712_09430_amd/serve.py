@@ -13,9 +13,17 @@ are fetched afterwards (Sec. 3.1: estimate the output buffer, fetch the rest
 later).  Batches on different slots overlap on the device (Sec. 3.2: several
 independent tracker instances on one GPU).
 
-Admission is bounded by an HBM budget: the slots' preallocated footprint
-(workspace + input + output buffers) must fit in it, which fixes how many
-slots run at once; a batch never exceeds its slot's capacity.
+Admission is bounded by an HBM budget (Sec. 3.2: further events go onto the
+GPU as long as its memory suffices).  Every in-flight batch is charged its
+footprint by the paper's memory model (Sec. 4.1: the tracker's internal
+memory is about three times its input): input + 3 x input + outputs (links,
+start list, and the estimated tracklet records), from the batch's own hit
+and sector counts.  A free slot takes the waiting events (FIFO) only as far
+as the in-flight footprint stays within the budget; an arrived event that
+does not fit waits for a completion (a budget deferral), even with a slot
+free.  The number of slots is how many batches of the stream's largest event
+fit in the budget, at most `n_slots`; each slot's buffers are allocated once,
+for its capacity (`slot_hits`, `slot_sectors`).
 
 Latency of an event = completion of its batch (results in host memory)
 minus its arrival time.  Nothing here computes tracking results: every step
@@ -97,11 +105,17 @@ class Slot:
         self.late_fetches = 0
         self.inp = C.catpc_input()
 
-    def footprint(self):
+    def reserved(self):
+        """Device bytes the slot holds: workspace, input and output buffers."""
         ws = C.catpc_workspace_bytes(self.n_rows, self.max_hits, self.max_sectors)
         inputs = 12 * self.max_hits + 8 * (self.max_sectors + 1)
         outputs = 12 * self.max_hits + 8 * (self.max_sectors + 1) + self.cap * (BYTES_PER_TRACKLET + 4 * self.out.row_stride)
         return ws + inputs + outputs
+
+    def charge(self, n_hits, n_sectors):
+        """Footprint of a batch of n_hits hits in n_sectors sectors."""
+        est = min(self.est, max(256, int(self.out_frac * n_hits)))
+        return batch_footprint(n_hits, n_sectors, est, self.out.row_stride)
 
     def submit(self, stream_src, e0, e1):
         """Enqueue events [e0, e1) of the stream: H2D of each event's hits into
@@ -140,6 +154,7 @@ class Slot:
             self.done.record(self.stream)
         self.busy = True
         self.events = (e0, e1, ns, est)
+        self.charged = self.charge(n, ns)
 
     def collect(self, keep):
         """After the batch completed: status check, late fetch of tracklets
@@ -167,6 +182,15 @@ class Slot:
         return n_trk, res
 
 
+def batch_footprint(n_hits, n_sectors, est_tracklets, row_stride):
+    """HBM charged to a batch: input (y, z, row, sector offsets) + three
+    times the input for the tracker's internal memory + outputs (links and
+    start list, per-sector tracklet offsets, the estimated tracklet records)."""
+    inp = 12 * n_hits + 8 * (n_sectors + 1)
+    out = 12 * n_hits + 8 * (n_sectors + 1) + est_tracklets * (BYTES_PER_TRACKLET + 4 * row_stride)
+    return inp + 3 * inp + out
+
+
 class _Sizes:
     def __init__(self, n_hits, n_sectors):
         self.n_hits, self.n_sectors = n_hits, n_sectors
@@ -176,21 +200,21 @@ def serve(stream_src, n_slots=3, slot_hits=4_000_000, slot_sectors=36 * 24, hbm_
           params=None, tuning=None, device="cuda:0", out_frac=0.03, keep_results=False, keep_rows=False,
           warmup_events=0, realtime=True):
     """Run the event stream; returns a dict with per-event latency (s), batch
-    sizes, sustained hits/s and (optionally) per-event results."""
+    sizes, sustained hits/s, the in-flight footprint and budget deferrals, and
+    (optionally) per-event results."""
     S = stream_src
     if int(S.ev_hits.max(initial=0)) > slot_hits or int(S.ev_secs.max(initial=0)) > slot_sectors:
         raise ValueError("an event exceeds the slot capacity")
-    slots = []
-    used = 0
-    for _ in range(n_slots):
-        sl = Slot(S.row_x, slot_hits, slot_sectors, params, tuning, device, out_frac, keep_rows)
-        if slots and used + sl.footprint() > hbm_budget:
-            sl.tracker.close()
-            break
-        if not slots and sl.footprint() > hbm_budget:
-            raise ValueError("one slot does not fit in the HBM budget")
-        used += sl.footprint()
-        slots.append(sl)
+    first = Slot(S.row_x, slot_hits, slot_sectors, params, tuning, device, out_frac, keep_rows)
+    full = first.charge(slot_hits, slot_sectors)
+    biggest = max(first.charge(int(h), int(k)) for h, k in zip(S.ev_hits, S.ev_secs)) if S.n_events else 1
+    if biggest > hbm_budget:
+        first.tracker.close()
+        raise ValueError("an event's footprint exceeds the HBM budget")
+    # as many slots as batches of the largest event fit in the budget, at most n_slots
+    want = max(1, min(n_slots, hbm_budget // biggest))
+    slots = [first] + [Slot(S.row_x, slot_hits, slot_sectors, params, tuning, device, out_frac, keep_rows)
+                       for _ in range(want - 1)]
     torch.cuda.synchronize(device)
     n = S.n_events
     done_t = np.zeros(n)
@@ -199,6 +223,9 @@ def serve(stream_src, n_slots=3, slot_hits=4_000_000, slot_sectors=36 * 24, hbm_
     batches = []
     nxt = 0          # next event not yet admitted
     finished = 0
+    in_flight = 0    # footprint charged to the batches on the device
+    peak = 0
+    deferred = set()  # events that waited with a slot free because the budget was spent
     t0 = time.perf_counter()
     while finished < n:
         now = time.perf_counter() - t0
@@ -207,12 +234,13 @@ def serve(stream_src, n_slots=3, slot_hits=4_000_000, slot_sectors=36 * 24, hbm_
             if sl.busy and sl.done.query():
                 e0, e1 = sl.events[0], sl.events[1]
                 n_trk, res = sl.collect(keep_results)
+                in_flight -= sl.charged
                 tdone = time.perf_counter() - t0
                 done_t[e0:e1] = tdone
                 finished += e1 - e0
                 if keep_results:
                     split_events(S, e0, e1, res, results)
-        # admissions: arrived events go into free slots as whole FIFO batches
+        # admissions: arrived events go into free slots as whole FIFO batches, within the budget
         if not realtime:
             now = float("inf")
         for sl in slots:
@@ -221,9 +249,16 @@ def serve(stream_src, n_slots=3, slot_hits=4_000_000, slot_sectors=36 * 24, hbm_
             e1 = nxt
             while (e1 < n and S.arrival[e1] <= now and
                    S.hit_start[e1 + 1] - S.hit_start[nxt] <= sl.max_hits and
-                   S.sec_start[e1 + 1] - S.sec_start[nxt] <= sl.max_sectors):
+                   S.sec_start[e1 + 1] - S.sec_start[nxt] <= sl.max_sectors and
+                   in_flight + sl.charge(int(S.hit_start[e1 + 1] - S.hit_start[nxt]),
+                                         int(S.sec_start[e1 + 1] - S.sec_start[nxt])) <= hbm_budget):
                 e1 += 1
+            if e1 == nxt:  # the next event does not fit in what is left of the budget
+                deferred.add(nxt)
+                break
             sl.submit(S, nxt, e1)
+            in_flight += sl.charged
+            peak = max(peak, in_flight)
             batch_of[nxt:e1] = len(batches)
             batches.append(e1 - nxt)
             nxt = e1
@@ -239,7 +274,10 @@ def serve(stream_src, n_slots=3, slot_hits=4_000_000, slot_sectors=36 * 24, hbm_
            "p99_ms": float(np.percentile(lat[w], 99) * 1e3) if n > warmup_events else None,
            "hits_per_s": hits / span if span > 0 else None, "n_events": n - warmup_events,
            "batches": len(batches), "mean_batch_events": float(np.mean(batches)) if batches else 0.0,
-           "slots": len(slots), "slot_footprint_bytes": slots[0].footprint(), "hbm_budget_bytes": hbm_budget,
+           "batch_of": batch_of, "slots": len(slots), "slot_reserved_bytes": slots[0].reserved(),
+           "full_batch_footprint_bytes": full, "hbm_budget_bytes": hbm_budget,
+           "peak_in_flight_bytes": peak, "deferred_events": len(deferred),
+           "largest_event_footprint_bytes": biggest,
            "late_fetches": sum(sl.late_fetches for sl in slots),
            "results": results}
     for sl in slots:

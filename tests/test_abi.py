@@ -70,3 +70,52 @@ def test_host_validation(lib):
 def test_row_stride(lib):
     assert [C.catpc_row_stride(n) for n in (1, 7, 8, 9, 159, 160)] == [8, 8, 8, 16, 160, 160]
     assert C.catpc_row_stride(0) == 0
+
+
+def test_sector_frames_follow_the_generator(lib):
+    """catpc_sector_frame agrees with the event generator's own sector
+    rotations (2 x 18 sectors, Sec. 2) and sides."""
+    import synth
+    g = C.catpc_geometry_of(synth.row_x())
+    for s in range(36):
+        a, side = C.catpc_sector_frame(g, s)
+        assert a == pytest.approx(synth.sector_alpha(s), abs=1e-12)
+        assert side == (1 if s < 18 else -1)
+    for s in (-1, 36):
+        with pytest.raises(C.CatpcError):
+            C.catpc_sector_frame(g, s)
+
+
+def test_to_global_matches_the_closed_form_helix(lib):
+    """Sector-frame parameters of generator helices (closed form, evaluated
+    in the sector's rotated frame) map to the same helix evaluated in the
+    global frame: position, momentum azimuth (also from a finite difference
+    along the helix), dip and curvature."""
+    import math
+
+    import numpy as np
+
+    import synth
+    g = C.catpc_geometry_of(synth.row_x())
+    # (q/pT, tan lambda, launch angle from the sector's centre, sector, path):
+    # tracks leaving the origin through their sector, as the tracker sees them
+    cases = [(1.0 / 0.5, 0.3, 0.05, 5, 120.0), (-1.0 / 2.0, -0.8, -0.1, 23, 200.0), (1.0 / 8.0, 0.0, 0.12, 17, 90.0),
+             (-1.0 / 0.3, 1.0, -0.02, 30, 150.0)]
+    for qpt, tanl, dphi, s, path in cases:
+        a = synth.sector_alpha(s)
+        phi0 = a + dphi
+        x, y, z, sp = synth.helix_point(qpt, tanl, phi0, synth.BZ, a, path)
+        X, Y, Z, SP = synth.helix_point(qpt, tanl, phi0, synth.BZ, 0.0, path)
+        o = C.catpc_to_global(g, s, [x], [[y, z, sp, tanl, qpt]])[0]
+        tol = 4e-5 * max(1.0, abs(x), abs(y), abs(z))  # binary32 inputs
+        assert o[0] == pytest.approx(X, abs=tol) and o[1] == pytest.approx(Y, abs=tol)
+        assert o[2] == pytest.approx(Z, abs=tol)
+        assert math.sin(o[3]) == pytest.approx(SP, abs=1e-6)
+        p1 = synth.helix_point(qpt, tanl, phi0, synth.BZ, 0.0, path + 1e-4)
+        p0 = synth.helix_point(qpt, tanl, phi0, synth.BZ, 0.0, path - 1e-4)
+        d = math.atan2(p1[1] - p0[1], p1[0] - p0[0])
+        assert math.remainder(o[3] - d, 2 * math.pi) == pytest.approx(0.0, abs=1e-6)
+        assert -math.pi < o[3] <= math.pi
+        assert o[4] == np.float32(tanl) and o[5] == np.float32(qpt)
+    with pytest.raises(C.CatpcError):
+        C.catpc_to_global(g, 0, [100.0], [[0.0, 0.0, 1.5, 0.0, 0.0]])

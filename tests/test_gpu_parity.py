@@ -87,12 +87,14 @@ def test_small_uneven_batch_bit_exact():
     check_batch(b)
 
 
-def test_work_counts_match_oracle_counters():
+@pytest.mark.parametrize("sync", [0, 1])
+def test_work_counts_match_oracle_counters(sync):
     """The tracklet kernel's own count of transports, updates, gated
-    candidates and row searches equals the oracle's count on the same data."""
+    candidates and row searches equals the oracle's count on the same data,
+    whatever the kernel's schedule."""
     _torch()
     b = synth.batch_workload(seed=13, n_events=2, lo=50, hi=1500)
-    tr, hits, out, st, n = run_gpu(b)
+    tr, hits, out, st, n = run_gpu(b, tuning={"tc_sync": sync})
     got = tr.work_counts()
     want = np.zeros(4, np.int64)
     for s in range(b.n_sectors):
@@ -135,7 +137,9 @@ def test_tuning_does_not_change_results():
                 {"bin_hits": 1.0, "nf_block": 256, "tc_block": 256, "tc_waves_per_cu": 3, "use_graph": 1,
                  "nf_rows": 3, "nf_lds_kb": 8, "tc_xcd": 1, "tc_occupancy": 6, "tc_sync": 1},
                 {"bin_hits": 0.5, "nf_block": 64, "tc_block": 64, "tc_waves_per_cu": 2, "use_graph": 0,
-                 "nf_rows": 2, "nf_lds_kb": 32, "tc_xcd": 0, "tc_occupancy": 6}):
+                 "nf_rows": 2, "nf_lds_kb": 32, "tc_xcd": 0, "tc_occupancy": 6},
+                {"bin_hits": 2.0, "nf_block": 256, "tc_block": 256, "tc_waves_per_cu": 8, "use_graph": 1,
+                 "nf_rows": 32, "nf_lds_kb": 24, "tc_xcd": 1, "tc_occupancy": 0}):
         _, _, out, st, n = run_gpu(b, tuning=tun)
         assert n == n0
         l1, t1 = out.links_numpy(), out.tracklets_numpy(n)
@@ -333,6 +337,48 @@ def test_precision_form_bit_exact():
         _, _, _, n, _, trk = check_batch(b, params=p)
         if prec == 2:
             assert np.all(trk["flags"] & C.FLAG_REFIT64)
+
+
+def _spd64(c):
+    """Positive pivots of both covariance blocks in binary64 (packed lower
+    triangle: transverse y, sin phi, q/pT; longitudinal z, tan lambda)."""
+    t = np.array([[c[0], c[3], c[10]], [c[3], c[5], c[12]], [c[10], c[12], c[14]]], np.float64)
+    lo = np.array([[c[2], c[7]], [c[7], c[9]]], np.float64)
+    try:
+        np.linalg.cholesky(t)
+        np.linalg.cholesky(lo)
+    except np.linalg.LinAlgError:
+        return False
+    return True
+
+
+@pytest.mark.parametrize("sigma", [5e-4, 3e-4])
+def test_precision_form_repairs_real_spd_failures(sigma):
+    """Precise clusters (smear and fit error sigma cm in both coordinates)
+    drive some binary32 covariances to a non-positive pivot: the precision
+    form (Sec. 2 item 2; binary32 filter, binary64 covariance only for the
+    tracklets that fail the check) refits exactly those, bit for bit as the
+    oracle does, and their stored covariances are positive definite."""
+    _torch()
+    from paper_1712_09430_amd import catpc as C
+    b = synth.sector_workload(seed=11, sigma=sigma)
+    flags = {}
+    for prec in (0, 1):
+        p = C.catpc_default_params()
+        p.sigma_y = p.sigma_z = sigma
+        p.precision = prec
+        _, _, _, n, _, trk = check_batch(b, params=p)
+        flags[prec] = trk["flags"]
+        fail = np.flatnonzero(trk["flags"] & C.FLAG_SPD_FAIL)
+        assert len(fail) >= 1
+        refit = (trk["flags"] & C.FLAG_REFIT64) != 0
+        if prec == 0:
+            assert not refit.any()
+            assert not any(_spd64(trk["cov"][i]) for i in fail)
+        else:
+            assert np.array_equal(np.flatnonzero(refit), fail)
+            assert all(_spd64(trk["cov"][i]) for i in fail)
+    assert np.array_equal(flags[0] & C.FLAG_SPD_FAIL, flags[1] & C.FLAG_SPD_FAIL)
 
 
 def test_invariants_and_one_hypothesis_per_seed():

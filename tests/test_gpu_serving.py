@@ -47,7 +47,76 @@ def test_small_budget_runs_with_one_slot():
     pool = synth.event_pool(seed=6, n_events=3, lo=20, hi=300)
     src = serve.EventStream(pool, [0, 1, 2, 0, 1, 2], serve.poisson_arrivals(6, 2000.0, seed=3), pool[0].row_x)
     probe = serve.Slot(pool[0].row_x, 200_000, 36 * 4, None, None, "cuda:0", 0.01, False)
-    fp = probe.footprint()
+    big = max(probe.charge(int(h), int(k)) for h, k in zip(src.ev_hits, src.ev_secs))
     probe.tracker.close()
-    res = serve.serve(src, n_slots=4, slot_hits=200_000, slot_sectors=36 * 4, hbm_budget=int(1.5 * fp))
+    res = serve.serve(src, n_slots=4, slot_hits=200_000, slot_sectors=36 * 4, hbm_budget=int(1.5 * big),
+                      out_frac=0.01)
     assert res["slots"] == 1 and res["n_events"] == 6
+    assert res["peak_in_flight_bytes"] <= int(1.5 * big)
+
+
+def _oracle_event(ev, P):
+    """The oracle's tracklets of every sector of one event, concatenated the
+    way the GPU output is (per-sector offsets, then the records)."""
+    import oracle
+    toff, recs = [0], {k: [] for k in ("x_ref", "param", "cov", "start_row", "first_row", "last_row", "n_hits",
+                                       "flags", "row_hit")}
+    for s in range(ev.n_sectors):
+        sec = ev.sector(s)
+        o = oracle.track_sector(sec["y"], sec["z"], sec["row"], ev.row_x, P, "f32")
+        toff.append(toff[-1] + len(o["start"]))
+        for k in recs:
+            recs[k].append(o[k])
+    return np.array(toff), {k: np.concatenate(v) for k, v in recs.items()}
+
+
+def test_budget_defers_admission_and_results_stay_exact():
+    """With room in the budget for only part of what the free slots would
+    take, admissions wait for completions (events deferred with a slot
+    free), the in-flight footprint never exceeds the budget, every event's
+    result is bit-identical to the event served alone, and one event of each
+    batch size equals the oracle."""
+    import oracle
+    from paper_1712_09430_amd import serve
+    pool = synth.event_pool(seed=7, n_events=5, lo=100, hi=1500)
+    rng = np.random.default_rng(4)
+    order = rng.integers(0, len(pool), 30)
+    arrival = serve.poisson_arrivals(len(order), 20000.0, seed=5)
+    src = serve.EventStream(pool, order, arrival, pool[0].row_x)
+    probe = serve.Slot(pool[0].row_x, 1_500_000, 36 * 8, None, None, "cuda:0", 0.01, False)
+    big = max(probe.charge(int(h), int(k)) for h, k in zip(src.ev_hits, src.ev_secs))
+    probe.tracker.close()
+    budget = int(2.5 * big)
+    mix = serve.serve(src, n_slots=3, slot_hits=1_500_000, slot_sectors=36 * 8, hbm_budget=budget,
+                      keep_results=True, keep_rows=True, out_frac=0.01)
+    assert mix["slots"] == 2
+    assert mix["deferred_events"] > 0
+    assert 0 < mix["peak_in_flight_bytes"] <= budget
+    alone = {}
+    for p in range(len(pool)):
+        one = serve.EventStream(pool, [p], [0.0], pool[0].row_x)
+        alone[p] = serve.serve(one, n_slots=1, slot_hits=1_500_000, slot_sectors=36 * 8, keep_results=True,
+                               keep_rows=True)["results"][0]
+    for e, p in enumerate(order):
+        got, want = mix["results"][e], alone[p]
+        assert np.array_equal(got["toff"], want["toff"]) and np.array_equal(got["rows"], want["rows"])
+        for f, v in want["trk"].items():
+            assert np.array_equal(got["trk"][f].view(np.uint8), v.view(np.uint8)), f
+    # one served event per batch size against the oracle
+    sizes = np.bincount(mix["batch_of"])
+    checked = set()
+    P = oracle.Params()
+    for e, p in enumerate(order):
+        k = int(sizes[mix["batch_of"][e]])
+        if k in checked:
+            continue
+        checked.add(k)
+        toff, o = _oracle_event(pool[p], P)
+        got = mix["results"][e]
+        assert np.array_equal(got["toff"], toff)
+        assert np.array_equal(got["rows"], o["row_hit"])
+        for f in ("x_ref", "param", "cov"):
+            assert np.array_equal(got["trk"][f].view(np.uint8), o[f].view(np.uint8)), f
+        for f in ("start_row", "first_row", "last_row", "n_hits", "flags"):
+            assert np.array_equal(got["trk"][f], o[f]), f
+    assert len(checked) >= 2

@@ -1,5 +1,5 @@
-"""Pins for the tracklet-selection oracle (Sec. 2 item 2: of several seeds
-followed along one track segment the best instance stays, the others go).
+"""Pins for the tracklet-selection oracle (Sec. 2 item 2: duplicate
+tracklets grown from several seeds of one segment reduce to one).
 Hand-built cases decide every rule of the reading (weight = hit count, ties
 to the smaller tracklet, invalid tracklets take no part, a tracklet needs
 min_hits hits of its own, dropped tracklets hand nothing on); properties hold

@@ -167,3 +167,92 @@ def test_precision_form_refit():
     assert_parameters(allr["param"][good], ref["param"][good], ref["cov"][good], "precision form")
     m = oracle.refit_mixed(s["y"], s["z"], b.row_x, base["row_hit"], base["start_row"], P)
     assert np.array_equal(m["param"], allr["param"]) and np.all(m["spd_ok"] == 1)
+
+
+def _spd64(c):
+    t = np.array([[c[0], c[3], c[10]], [c[3], c[5], c[12]], [c[10], c[12], c[14]]], np.float64)
+    lo = np.array([[c[2], c[7]], [c[7], c[9]]], np.float64)
+    try:
+        np.linalg.cholesky(t)
+        np.linalg.cholesky(lo)
+    except np.linalg.LinAlgError:
+        return False
+    return True
+
+
+def test_precision_form_repairs_real_failures():
+    """Precise clusters (smear and fit error 3e-4 cm) make the binary32
+    covariance of some tracklets lose positive definiteness (reading: the
+    positivity check takes binary32 Cholesky pivots of both blocks).  The
+    flag agrees with a binary64 Cholesky of the stored covariance, and the
+    precision form refits exactly the flagged tracklets on their recorded
+    hits into a positive definite covariance, leaving hits, rows and every
+    other tracklet unchanged."""
+    sig = 3e-4
+    b = synth.sector_workload(seed=11, sigma=sig)
+    s = b.sector(0)
+    p0 = oracle.Params(sigma_y=sig, sigma_z=sig)
+    p1 = oracle.Params(sigma_y=sig, sigma_z=sig, precision=1)
+    base = oracle.track_sector(s["y"], s["z"], s["row"], b.row_x, p0, "f32")
+    fix = oracle.track_sector(s["y"], s["z"], s["row"], b.row_x, p1, "f32")
+    fail = np.flatnonzero(base["flags"] & oracle.SPD_FAIL)
+    assert len(fail) >= 1
+    assert not any(_spd64(base["cov"][i]) for i in fail)
+    assert all(_spd64(base["cov"][i]) for i in np.flatnonzero(~base["flags"] & oracle.SPD_FAIL))
+    assert np.array_equal(np.flatnonzero(fix["flags"] & oracle.REFIT64), fail)
+    assert all(_spd64(fix["cov"][i]) for i in fail)
+    for k in ("row_hit", "n_hits", "first_row", "last_row", "start_row"):
+        assert np.array_equal(fix[k], base[k]), k
+    keep = np.ones(len(base["flags"]), bool)
+    keep[fail] = False
+    assert np.array_equal(fix["param"][keep], base["param"][keep])
+    assert np.array_equal(fix["cov"][keep], base["cov"][keep])
+    m = oracle.refit_mixed(s["y"], s["z"], b.row_x, base["row_hit"][fail], base["start_row"][fail], p0)
+    assert np.array_equal(m["param"], fix["param"][fail]) and np.all(m["spd_ok"] == 1)
+
+
+def test_normalised_innovation_averages_one():
+    """Statistical consistency of the filter (Sec. 2 item 2, the Kalman
+    update): on tracklets whose every hit comes from one generated track,
+    replay the outward pass in binary64 with the oracle's own init, transport
+    and update, and take the normalised innovation r^2 / (C + sigma^2) of each
+    scalar update before it is applied.  Its mean is 1 and its median that of
+    chi^2 with one degree of freedom (0.455) for y and for z.  The update at
+    the start hit's upward neighbour is left out: the chord initialisation
+    passes through that hit, so its residual is zero by construction."""
+    sy2, sz2 = P.sigma_y ** 2, P.sigma_z ** 2
+    nu_y, nu_z = [], []
+    for seed in (11, 12):
+        b = synth.sector_workload(seed=seed, truth=True)
+        s = b.sector(0)
+        o = oracle.track_sector(s["y"], s["z"], s["row"], b.row_x, P, "f64")
+        lab = s["label"]
+        for t in range(len(o["start"])):
+            rh = o["row_hit"][t]
+            hits = rh[rh >= 0]
+            if not o["flags"][t] & oracle.VALID or lab[hits[0]] < 0 or np.any(lab[hits] != lab[hits[0]]):
+                continue
+            r0 = o["start_row"][t]
+            last = int(np.flatnonzero(rh >= 0).max())
+            h0, h1 = rh[r0], rh[r0 + 1]
+            st, rc = oracle.init_state([b.row_x[r0], s["y"][h0], s["z"][h0]],
+                                       [b.row_x[r0 + 1], s["y"][h1], s["z"][h1]], P)
+            assert rc == 0
+            for r in range(r0 + 1, last + 1):
+                st, rc = oracle.propagate(st, b.row_x[r], P)
+                if rc:
+                    break
+                h = rh[r]
+                if h < 0:
+                    continue
+                if r > r0 + 1:
+                    nu_y.append((s["y"][h] - st[1]) ** 2 / (st[6] + sy2))
+                    nu_z.append((s["z"][h] - st[2]) ** 2 / (st[12] + sz2))
+                st, rc = oracle.update(st, s["y"][h], s["z"][h], P)
+                if rc:
+                    break
+    nu_y, nu_z = np.array(nu_y), np.array(nu_z)
+    assert len(nu_y) > 20000
+    for nu in (nu_y, nu_z):
+        assert 0.93 < nu.mean() < 1.07, nu.mean()
+        assert 0.42 < np.median(nu) < 0.49, np.median(nu)
