@@ -374,6 +374,27 @@ catpc_status catpc_merge_counts(catpc_ctx* ctx, void* stream, int64_t* n_pairs, 
  * skipped); CATPC_E_STATE without a selection since the last track call. */
 catpc_status catpc_select_result(catpc_ctx* ctx, void* stream, int64_t* n_tracks, int64_t* n_track_hits);
 
+/* The batched form without any allocation, for callers that cannot allocate
+ * device or pinned memory: code being captured into a HIP graph, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same stage chain, results
+ * and tuning as catpc_track_batch (launched directly, no graph), without a
+ * context: the workspace is a fixed 96 MiB device array inside the library,
+ * one copy per device, held until the process ends -- enough for about
+ * 1.9 M hits in 36 sectors of 159 pad rows (a central event); larger inputs
+ * are rejected with CATPC_E_INVALID (nothing enqueued).  row_x: DEVICE
+ * [n_rows], the pad-row planes; params / tuning: host (tuning NULL = the
+ * defaults).  status: DEVICE uint64, written at the end of the chain with the
+ * error bits found on the device (1: hits not row-sorted or a row out of
+ * range; 8: x differs from the row planes; 64: row_x not positive and
+ * strictly ascending; 0: none).  The number of tracklets is
+ * tracklet_offset[n_sectors]; slots beyond tracklet_capacity are not
+ * written (no late fetch).  Asynchronous on `stream`.  Every call on a
+ * device shares that device's array: calls that overlap on one device (other
+ * streams, other threads) race and must be serialised by the caller. */
+catpc_status catpc_track_batch_noalloc(int32_t n_rows, const float* row_x, const catpc_params* params,
+                                       const catpc_tuning* tuning, const catpc_input* in, const catpc_output* out,
+                                       uint64_t* status, void* stream);
+
 /* Achievable-peak probes (measurement only, no tracking): a device copy of
  * n_bytes (a multiple of 16; 16-byte aligned device pointers), and in each of
  * n_threads threads 8 independent chains of n_iter binary32 fused

@@ -22,7 +22,7 @@ FLAG_VALID, FLAG_STOP_SINPHI, FLAG_STOP_ARC, FLAG_SPD_FAIL, FLAG_REFIT64 = 1, 2,
 N_STAGES = 8
 STAGES = ("row_index", "grid", "neighbours", "clean_start", "scan", "compact", "tracklets", "refit64")
 
-EXPORTS = ("catpc_sector_frame", "catpc_to_global", "catpc_stage_times", "catpc_work_counts", "catpc_default_params", "catpc_default_tuning", "catpc_row_stride", "catpc_workspace_bytes", "catpc_create", "catpc_destroy",
+EXPORTS = ("catpc_track_batch_noalloc", "catpc_sector_frame", "catpc_to_global", "catpc_stage_times", "catpc_work_counts", "catpc_default_params", "catpc_default_tuning", "catpc_row_stride", "catpc_workspace_bytes", "catpc_create", "catpc_destroy",
            "catpc_set_params", "catpc_set_tuning", "catpc_get_tuning", "catpc_track_batch", "catpc_track_plain",
            "catpc_result", "catpc_fetch_tracklets", "catpc_select_tracklets", "catpc_select_result", "catpc_refit_tracks", "catpc_default_merge_params", "catpc_merge_tracks", "catpc_merge_counts", "catpc_fp32_probe", "catpc_probe_copy", "catpc_probe_fma",
            "catpc_last_error")
@@ -107,6 +107,9 @@ def lib():
         L.catpc_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]
         L.catpc_workspace_bytes.restype = ctypes.c_size_t
         L.catpc_create.argtypes = [P(catpc_geometry), P(catpc_params), ctypes.c_int64, ctypes.c_int32, P(_vp)]
+        L.catpc_track_batch_noalloc.argtypes = [ctypes.c_int32, _vp, P(catpc_params), P(catpc_tuning), _vp, _vp,
+                                                 _vp, _vp]
+        L.catpc_track_batch_noalloc.restype = st
         L.catpc_sector_frame.argtypes = [P(catpc_geometry), ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int32)]
         L.catpc_sector_frame.restype = st
         L.catpc_to_global.argtypes = [P(catpc_geometry), ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp]
@@ -206,6 +209,14 @@ def catpc_create(row_x, params, max_hits, max_sectors, sectors_per_side=18):
     _check(lib().catpc_create(ctypes.byref(g), ctypes.byref(params), int(max_hits), int(max_sectors),
                               ctypes.byref(h)))
     return h
+
+
+def catpc_track_batch_noalloc(n_rows, row_x_dev, params, tuning, inp, out, status_dev, stream):
+    """The batched chain on the library's fixed workspace (no allocation);
+    row_x_dev and status_dev are device addresses, tuning may be None."""
+    _check(lib().catpc_track_batch_noalloc(int(n_rows), row_x_dev, ctypes.byref(params),
+                                           ctypes.byref(tuning) if tuning is not None else None,
+                                           ctypes.byref(inp), ctypes.byref(out), status_dev, stream))
 
 
 def catpc_sector_frame(geom, sector_id):

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1009,3 +1010,98 @@ catpc_status catpc_probe_fma(float* out, int64_t n_threads, int32_t n_iter, void
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ no allocation
+// The workspace of catpc_track_batch_noalloc: a fixed device array in the
+// library, one copy on each device the library runs on, held until the
+// process ends.  Host code never uses this name as an address (in host code it
+// is a stand-in, not the device array): the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)96 << 20;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+int g_scratch_cu[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device) and the device's compute-unit count.
+catpc_status scratch_here(char** base, int* n_cu) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CATPC_E_INVALID, "device id beyond the library's table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress");
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0) ncu = 256;
+    g_scratch_cu[dev] = ncu;
+    g_scratch[dev] = (char*)p;
+  }
+  *base = g_scratch[dev];
+  *n_cu = g_scratch_cu[dev];
+  return CATPC_OK;
+}
+
+}  // namespace
+
+extern "C" catpc_status catpc_track_batch_noalloc(int32_t n_rows, const float* row_x, const catpc_params* params,
+                                                  const catpc_tuning* tuning, const catpc_input* in,
+                                                  const catpc_output* out, uint64_t* status, void* stream) {
+  if (n_rows < 3 || n_rows > kMaxRows || !row_x) return fail(CATPC_E_INVALID, "need 3 <= n_rows <= 4096 and row_x");
+  catpc_status rc = check_params(params);
+  if (rc) return rc;
+  catpc_tuning t;
+  catpc_default_tuning(&t);
+  if (tuning) {
+    rc = check_tuning(tuning);
+    if (rc) return rc;
+    t = *tuning;
+  }
+  t.use_graph = 0;
+  if (!status) return fail(CATPC_E_INVALID, "status is NULL");
+  if (!in || !out) return fail(CATPC_E_INVALID, "input or output is NULL");
+  if (in->n_hits < 0 || in->n_sectors < 0) return fail(CATPC_E_INVALID, "negative size");
+  const Layout L = plan(n_rows, in->n_hits, in->n_sectors, true);
+  const size_t need = align_up(L.total) + sizeof(float4) * (size_t)n_rows;
+  if (need > kScratchBytes)
+    return fail(CATPC_E_INVALID, "input needs " + std::to_string(need) + " bytes of workspace; the fixed workspace "
+                                 "holds " + std::to_string(kScratchBytes) + " (about 1.9 M hits in 36 sectors of 159 "
+                                 "pad rows)");
+  rc = check_io_within(in->n_hits, in->n_sectors, in, out, false);
+  if (rc) return rc;
+  char* base = nullptr;
+  int n_cu = 256;
+  rc = scratch_here(&base, &n_cu);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  Chain c;
+  c.n_rows = n_rows;
+  c.row_x = row_x;
+  c.rowk = reinterpret_cast<const float4*>(base + align_up(L.total));
+  c.consts = make_consts(*params);
+  c.precision = params->precision;
+  c.tuning = t;
+  c.n_cu = n_cu;
+  c.ws = carve(base, L);
+  HIP_TRY(launch_reset(c.ws.counters, kNumCounters, st));
+  HIP_TRY(launch_rowk(row_x, n_rows, reinterpret_cast<float4*>(base + align_up(L.total)), c.ws.counters, st));
+  if (in->n_sectors > 0) {
+    const Span sp{0, in->n_sectors, 0, in->n_hits};
+    rc = enqueue_span(c, in, out, sp, st);
+    if (!rc) rc = enqueue_refit(c, in, out, sp, 0, st);
+    if (rc) return rc;
+  }
+  HIP_TRY(launch_status(c.ws.counters, status, st));
+  return CATPC_OK;
+}

@@ -84,7 +84,8 @@ constexpr int kCtrWork = 0;      // [0, kXcds): work counters of the tracklet ke
 constexpr int kCtrError = 8;     // bit 0: invalid rows seen; bit 1: selection saw only part of the tracklets;
                                  // bit 2: a tracklet record names a hit outside its sector; bit 3: x differs
                                  // from the row planes; bit 4: too many tracklets in a sector for the selection;
-                                 // bit 5: more tracks than the refit output holds
+                                 // bit 5: more tracks than the refit output holds; bit 6: pad-row planes given
+                                 // on the device are not positive and strictly ascending
 constexpr int kCtrCounts = 9;    // [9, 13): transports, updates, gated candidates, row searches
 constexpr int kCtrSelTracks = 13;  // selected tracks
 constexpr int kCtrSelHits = 14;    // hits they keep
@@ -167,6 +168,8 @@ constexpr float kBinMargin = 1.0e-2f;  // cm, widens bin ranges beyond rounding 
 
 // Launchers (kernels.hip).  All asynchronous on `st`.
 hipError_t launch_reset(unsigned long long* counters, int n, hipStream_t st);
+hipError_t launch_rowk(const float* row_x, int n_rows, float4* rowk, unsigned long long* counters, hipStream_t st);
+hipError_t launch_status(const unsigned long long* counters, uint64_t* status, hipStream_t st);
 hipError_t launch_row_index(const Inputs& in, Span sp, int n_rows, const float* row_x, const Workspace& ws,
                             int block, hipStream_t st);
 hipError_t launch_grid(const Inputs& in, Span sp, int n_rows, float bin_hits, const Workspace& ws, hipStream_t st);

@@ -70,6 +70,31 @@ __global__ void k_reset(unsigned long long* c, int n) {
   if ((int)threadIdx.x < n) c[threadIdx.x] = 0ull;
 }
 
+// Per-row neighbour-finder ratios from the pad-row planes on the device, each
+// one binary32 division (the same values the host computes for a context):
+// rowk[r] = (x_{r+1}/x_r, x_{r-1}/x_r, (x_r - x_{r-1}) / (x_{r+1} - x_{r-1}),
+// x_r) for 1 <= r <= R-2, (0, 0, 0, x_r) otherwise.  Planes that are not
+// positive and strictly ascending set error bit 6.
+__global__ void k_rowk(const float* __restrict__ row_x, int R, float4* __restrict__ rowk,
+                       unsigned long long* counters) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const float xr = row_x[r];
+  float4 v = make_float4(0.0f, 0.0f, 0.0f, xr);
+  if (r >= 1 && r + 1 < R) {
+    const float xu = row_x[r + 1], xd = row_x[r - 1];
+    v.x = xu / xr;
+    v.y = xd / xr;
+    v.z = (xr - xd) / (xu - xd);
+  }
+  rowk[r] = v;
+  if (!(xr > 0.0f) || (r > 0 && !(xr > row_x[r - 1]))) atomicOr(&counters[kCtrError], 64ull);
+}
+
+// Copy of the error word of the chain (kCtrError) to the caller.
+__global__ void k_status(const unsigned long long* counters, uint64_t* status) {
+  if (threadIdx.x == 0) *status = counters[kCtrError];
+}
 
 // --------------------------------------------------------------- row index
 // Blocks [0, item_blocks): one thread per (sector, row 0..R) item, first hit
@@ -2343,6 +2368,16 @@ inline unsigned blocks_for(int64_t n, int block) { return (unsigned)((n + block 
 // ================================================================ launchers
 hipError_t launch_reset(unsigned long long* counters, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, counters, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_rowk(const float* row_x, int n_rows, float4* rowk, unsigned long long* counters, hipStream_t st) {
+  hipLaunchKernelGGL(k_rowk, dim3(blocks_for(n_rows, 256)), dim3(256), 0, st, row_x, n_rows, rowk, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_status(const unsigned long long* counters, uint64_t* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, st, counters, status);
   return hipGetLastError();
 }
 

@@ -119,3 +119,26 @@ def test_to_global_matches_the_closed_form_helix(lib):
         assert o[4] == np.float32(tanl) and o[5] == np.float32(qpt)
     with pytest.raises(C.CatpcError):
         C.catpc_to_global(g, 0, [100.0], [[0.0, 0.0, 1.5, 0.0, 0.0]])
+
+
+def test_no_alloc_entry_point_validates_on_the_host(lib):
+    """catpc_track_batch_noalloc rejects, before touching the device, an input
+    beyond its fixed workspace and calls without a status word (host arrays
+    stand in for the device pointers: nothing is enqueued)."""
+    import numpy as np
+    rx = np.arange(85.0, 85.0 + 159.0, dtype=np.float32)
+    word = np.zeros(1, np.uint64)
+    inp, out = C.catpc_input(), C.catpc_output()
+    inp.n_sectors, inp.n_hits = 36, 3_000_000
+    p = C.catpc_default_params()
+    with pytest.raises(C.CatpcError) as e:
+        C.catpc_track_batch_noalloc(159, rx.ctypes.data, p, None, inp, out, word.ctypes.data, None)
+    assert e.value.status == C.CATPC_E_INVALID and "fixed workspace" in C.catpc_last_error()
+    inp.n_hits = 1000
+    with pytest.raises(C.CatpcError) as e:
+        C.catpc_track_batch_noalloc(159, rx.ctypes.data, p, None, inp, out, None, None)
+    assert "status" in C.catpc_last_error()
+    bad = C.catpc_default_tuning()
+    bad.nf_block = 1024
+    with pytest.raises(C.CatpcError):
+        C.catpc_track_batch_noalloc(159, rx.ctypes.data, p, bad, inp, out, word.ctypes.data, None)
