@@ -24,14 +24,16 @@ struct alignas(16) ChainHit {
 };
 
 // Per (sector, row) grid header, one 32-byte record: bin origin and bins per
-// cm, bin counts (ny == 0: empty row), global position of the row's first
-// sorted hit, and half the offset of its bin table (the table sits at
-// 2 * (first hit + row id), always even).
+// cm, bin counts (ny == 0: empty row; at most kMaxBinsPerRow each), global
+// position of the row's first sorted hit, half the offset of its bin table
+// (the table sits at 2 * (first hit + row id), always even), and the row's
+// hit count.
 struct alignas(32) RowHdr {
   float ymin, zmin, iby, ibz;
-  int32_t ny, nz;
+  int16_t ny, nz;
   int32_t hit_base;
   int32_t bin_half;
+  int32_t n;
 };
 
 // Method constants, every value already rounded the way the filter uses it.

@@ -180,7 +180,7 @@ __global__ __launch_bounds__(64) void k_grid(Inputs in, Span sp, int R, float bi
   const int64_t g = a + f0;
   if (n <= 0) {
     if (lane == 0) {
-      RowHdr h = {0.0f, 0.0f, 0.0f, 0.0f, 0, 0, (int32_t)g, (int32_t)(g + gid)};
+      RowHdr h = {0.0f, 0.0f, 0.0f, 0.0f, 0, 0, (int32_t)g, (int32_t)(g + gid), 0};
       ws.hdr[gid] = h;
     }
     return;
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(64) void k_grid(Inputs in, Span sp, int R, float bi
   const float zmin = Lz > 0.0f ? zlo : 0.0f;
   const int nb = ny * nz;
   if (lane == 0) {
-    RowHdr h = {ymin, zmin, iby, ibz, ny, nz, (int32_t)g, (int32_t)(g + gid)};
+    RowHdr h = {ymin, zmin, iby, ibz, (int16_t)ny, (int16_t)nz, (int32_t)g, (int32_t)(g + gid), n};
     ws.hdr[gid] = h;
   }
   for (int k = lane; k < nb; k += 64) cnt[k] = 0;
@@ -1087,16 +1087,11 @@ __device__ __forceinline__ int64_t take_slots(const Parts& P, int& k, unsigned l
   return -1;
 }
 
-// Start of a tracklet: its start hit (slot -> global hit), the chain record
-// of the start hit and of its upward neighbour, the seed state.
-struct Seed {
-  int64_t a;
-  int s, r0;
-  int32_t h0, h1, h2;  // start hit, its up neighbour, the one after (chain continues there)
-  float y1, z1;
-};
-
 constexpr int kTcMaxBlock = 256;
+
+// Bytes of the pad-row planes at the start of the tracklet kernels' dynamic
+// LDS (padded to 16 so that what follows stays 16-byte aligned).
+__host__ __device__ constexpr int tc_planes_bytes(int R) { return (R * 4 + 15) & ~15; }
 
 // Smallest / largest v over the wave's active lanes, 0 <= v < 2^16, from
 // ballots (the result is wave-uniform).
@@ -1116,27 +1111,158 @@ __device__ __forceinline__ int wave_max16(int v) {
   return m;
 }
 
+// LDS copy of one pad row's grid for a wave's searches (row-synchronous
+// form): the bin table from the 16-byte boundary at or below it, then the
+// row's sorted hits, copied straight from global memory into LDS
+// (global_load_lds, no registers) before the transport arithmetic, so the
+// search that follows the transport reads LDS instead of waiting on two
+// dependent global reads.  A row larger than kStageBytes is searched in place.
+constexpr int kStageBytes = 7168;  // per wave: rows of up to about 290 hits
+
+typedef __attribute__((address_space(1))) void* GlobalPtr;
+typedef __attribute__((address_space(3))) void* LdsPtr;
+
+struct StageLayout {
+  int off;   // ints between the 16-byte boundary and the row's first bin (0 or 2)
+  int bch;   // 16-byte chunks of bin table
+  int bytes; // header's first 16 bytes, bins, hits
+};
+
+// The staged copy of a row: [0, 16) the header's first half (bin origins and
+// bins per cm), then the bin table from the 16-byte boundary at or below it,
+// then the row's hits.
+__device__ __forceinline__ StageLayout stage_layout(int ny, int nz, int bin_half, int n) {
+  StageLayout L;
+  L.off = (2 * bin_half) & 3;
+  L.bch = (L.off + ny * nz + 1 + 3) >> 2;
+  L.bytes = 16 + 16 * L.bch + 16 * n;
+  return L;
+}
+
+// Second half of a row header as read ahead: (ny | nz << 16, hit_base,
+// bin_half, n).
+__device__ __forceinline__ int4 hdr_tail(const Workspace& ws, int64_t i) {
+  return reinterpret_cast<const int4*>(ws.hdr + i)[1];
+}
+
+// Issue the copies of row i into `reg` (wave-uniform; every lane of the wave
+// active: lane j of a copy instruction writes LDS bytes [16 j, 16 j + 16) of
+// its destination).  Reads stay inside the header, inside the bin table's
+// allocation (the 16-byte chunk holding its last int ends at most 12 bytes
+// past it, inside the table's padding) and inside the row's hits.
+__device__ __forceinline__ void stage_row(int64_t i, int hit_base, int bin_half, int n, const StageLayout& L,
+                                          const Workspace& ws, unsigned char* reg, int lane) {
+  if (lane == 0) __builtin_amdgcn_global_load_lds((GlobalPtr)(ws.hdr + i), (LdsPtr)reg, 16, 0, 0);
+  const int32_t* b0 = ws.bins + (2 * (int64_t)bin_half - L.off);
+  unsigned char* br = reg + 16;
+  for (int q = 0; q < L.bch; q += 64)
+    if (q + lane < L.bch)
+      __builtin_amdgcn_global_load_lds((GlobalPtr)(b0 + 4 * (q + lane)), (LdsPtr)(br + 16 * q), 16, 0, 0);
+  const SortedHit* h0 = ws.sorted + hit_base;
+  unsigned char* hr = br + 16 * L.bch;
+  for (int q = 0; q < n; q += 64)
+    if (q + lane < n)
+      __builtin_amdgcn_global_load_lds((GlobalPtr)(h0 + q + lane), (LdsPtr)(hr + 16 * q), 16, 0, 0);
+}
+
+// Wait for the wave's outstanding global memory operations (the LDS copies
+// among them: nothing else orders a later LDS read after them).
+__device__ __forceinline__ void stage_wait() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), other counters not waited
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Staging state of a wave (row-synchronous form): the staged row's bin counts
+// and layout, and the second half of the header of the row the wave steps to
+// next, read one row step ahead so that the copies of a row are issued
+// without waiting for its header.
+struct RowStage {
+  int ny, nz;
+  StageLayout L;
+  int4 pre;
+  int pre_s, pre_r;  // sector and row of `pre` (pre_s -1: none)
+};
+
+__device__ __forceinline__ RowGrid staged_row_grid(const RowStage& S, unsigned char* reg) {
+  const float4 f = *reinterpret_cast<const float4*>(reg);
+  RowGrid G;
+  G.ymin = f.x; G.zmin = f.y; G.iby = f.z; G.ibz = f.w;
+  G.ny = S.ny;
+  G.nz = S.nz;
+  G.bins = reinterpret_cast<const int32_t*>(reg + 16) + S.L.off;
+  G.hits = reinterpret_cast<const SortedHit*>(reg + 16 + 16 * S.L.bch);
+  return G;
+}
+
+// At the top of a row step, every lane of the wave active: stage row r of the
+// sector of the wave's first lane that searches there (`want`), when it fits,
+// and read ahead the header of row rnext.  Returns whether this lane's search
+// uses the copy.
+__device__ __forceinline__ bool stage_for(bool want, bool live, int s, int r, int rnext, int R, const Workspace& ws,
+                                          unsigned char* reg, int lane, RowStage& S) {
+  const unsigned long long m = __ballot(want);
+  const unsigned long long lv = __ballot(live);
+  const unsigned long long pick = m ? m : lv;
+  const int sw = __builtin_amdgcn_readlane(s, __ffsll((long long)pick) - 1);
+  const int ru = __builtin_amdgcn_readfirstlane(r);
+  bool mine = false;
+  if (m) {
+    const int64_t i = (int64_t)sw * R + ru;
+    const int4 t = (sw == S.pre_s && ru == S.pre_r) ? S.pre : hdr_tail(ws, i);
+    const int nyz = __builtin_amdgcn_readfirstlane(t.x);
+    S.ny = (int16_t)(nyz & 0xffff);
+    S.nz = (int16_t)(nyz >> 16);
+    if (S.ny > 0) {
+      const int hit_base = __builtin_amdgcn_readfirstlane(t.y);
+      const int bin_half = __builtin_amdgcn_readfirstlane(t.z);
+      const int n = __builtin_amdgcn_readfirstlane(t.w);
+      S.L = stage_layout(S.ny, S.nz, bin_half, n);
+      if (S.L.bytes <= kStageBytes) {
+        stage_row(i, hit_base, bin_half, n, S.L, ws, reg, lane);
+        mine = want && s == sw;
+      }
+    }
+  }
+  const int rn = __builtin_amdgcn_readfirstlane(rnext);
+  S.pre_s = -1;
+  if (rn >= 0 && rn < R) {
+    S.pre = hdr_tail(ws, (int64_t)sw * R + rn);
+    S.pre_s = sw;
+    S.pre_r = rn;
+  }
+  return mine;
+}
+
 // One tracklet: slot -> start hit -> seed chain -> following -> output.
-// kSync: the lanes of a wave walk the pad rows together (a lane whose pass
-// starts later waits), so that they read the same row grids at the same time;
+// Every lane of the wave calls it (`valid`: the lane has a slot).  kSync: the
+// lanes of a wave walk the pad rows together (a lane whose pass starts later
+// waits, a lane whose pass has ended idles), and the row every searching lane
+// of one sector needs is staged in LDS (`stage`, kStageBytes, this wave's);
 // each lane's own sequence of filter steps is the same either way.
 template <bool kSync>
-__device__ __forceinline__ void build_tracklet(const Inputs& in, Span sp, int R, const float* __restrict__ row_x, const Consts& c,
-                               const Workspace& ws, const int64_t* toff, int64_t slot, int64_t o,
-                               const TrackletOut& out, int RS, int32_t* chunk_lds, Work& w) {
-  const int s = ws.start_sec[slot];
-  const int64_t a = in.hit_offset[s];
-  const int64_t gi = ws.start_glob[slot];
+__device__ __forceinline__ void build_tracklet(const Inputs& in, int R, const float* __restrict__ row_x, const Consts& c,
+                                               const Workspace& ws, int64_t slot, int64_t o, bool valid,
+                                               const TrackletOut& out, int RS, int32_t* chunk_lds,
+                                               unsigned char* stage, Work& w) {
+  const int lane = threadIdx.x & 63;
+  int s = 0, r0 = 0;
+  int64_t a = 0, gi = 0;
+  if (valid) {
+    s = ws.start_sec[slot];
+    a = in.hit_offset[s];
+    gi = ws.start_glob[slot];
+    r0 = in.row[gi];
+  }
   const int32_t h0 = (int32_t)(gi - a);
-  const int r0 = in.row[gi];
   int32_t* rec = out.row_hit + o * RS;
-  (void)toff;
-  if (r0 < 1 || r0 > R - 3) {
-    // A start hit has an unlinked hit row below it and two linked rows above
-    // it, so on valid input it lies in rows 1 .. R-3.  Only a row value outside
-    // the sector's rows gets here (the row check has reported the input as
-    // invalid); the tracklet records nothing and writes nothing outside its
-    // own slot.
+  // A start hit has an unlinked hit row below it and two linked rows above
+  // it, so on valid input it lies in rows 1 .. R-3.  Only a row value outside
+  // the sector's rows fails this (the row check has reported the input as
+  // invalid); such a tracklet records nothing and writes nothing outside its
+  // own slot.
+  const bool in_range = valid && r0 >= 1 && r0 <= R - 3;
+  if (valid && !in_range) {
     for (int q = 0; q < RS / 8; ++q) chunk_store_none(q, rec);
     const Trk none = {};
     store_state(none, o, out);
@@ -1145,118 +1271,178 @@ __device__ __forceinline__ void build_tracklet(const Inputs& in, Span sp, int R,
     out.last_row[o] = -1;
     out.n_hits[o] = 0;
     out.flags[o] = 0;
-    return;
   }
-  const ChainHit c0 = ws.chain[gi];
-  const int32_t h1 = c0.up;
-  ChainHit nx = ws.chain[a + h1];  // next chain measurement
-  // the one after it, read one row step ahead so that the pointer chase
-  // along the chain overlaps a step of filter arithmetic (a start hit always
-  // has an up-link of its up-link)
-  ChainHit nn = nx;
-  if (nx.up >= 0) nn = ws.chain[a + nx.up];
+  ChainHit c0 = {0.0f, 0.0f, -1, 0}, nx = c0, nn = c0;
+  if (in_range) {
+    c0 = ws.chain[gi];
+    nx = ws.chain[a + c0.up];  // next chain measurement
+    // the one after it, read one row step ahead so that the pointer chase
+    // along the chain overlaps a step of filter arithmetic (a start hit
+    // always has an up-link of its up-link)
+    nn = nx;
+    if (nx.up >= 0) nn = ws.chain[a + nx.up];
+  }
   const int k0 = r0 >> 3;  // chunk of the start row
   RowChunk k = {chunk_lds + threadIdx.x, (int)blockDim.x, k0};
-  chunk_clear(k, k0);
-  chunk_set(k, r0, h0);
   int k_lo = k0, k_hi = k0;  // chunks written
   int fl = 0;
   int nh = 1, first_row = r0, lastr = r0;
-  Trk st, snap;  // running state; snap: the state the output takes
-  const int ei = init_track(st, row_x[r0], c0.y, c0.z, row_x[r0 + 1], nx.y, nx.z, c);
-  if (ei != kStepOk) {
-    fl |= stop_flag(ei);
-    snap = st;
-    chunk_store(k, rec);
-  } else {
+  Trk st = {}, snap = {};  // running state; snap: the state the output takes
+  bool ok_init = false;
+  if (in_range) {
+    chunk_clear(k, k0);
+    chunk_set(k, r0, h0);
+    const int ei = init_track(st, row_x[r0], c0.y, c0.z, row_x[r0 + 1], nx.y, nx.z, c);
     snap = st;  // outward: the state at the last update
-    // seed chain (no gate), then outward following
-    int32_t h = h1;
-    int miss = 0;
-    const int r_first = kSync ? wave_min16(r0 + 1) : r0 + 1;
-    for (int r = r_first; r < R; ++r) {
-      if (kSync && r <= r0) continue;  // waits for the wave's row
-      RowHdr hd;
-      if (h < 0) hd = ws.hdr[(int64_t)s * R + r];  // issued before the transport arithmetic
-      ++w.n_prop;
-      const int e = propagate(st, row_x[r], c);
-      if (e) { fl |= stop_flag(e); break; }
-      if ((r >> 3) != k.c) {
-        chunk_store(k, rec);
-        chunk_clear(k, r >> 3);
-        k_hi = r >> 3;
-      }
-      Pick j;
-      if (h >= 0) {
-        j.idx = h; j.y = nx.y; j.z = nx.z;
-      } else {
-        j = closest(st, grid_of(hd, ws), c, w);
-      }
-      if (j.idx >= 0) {
-        ++w.n_upd;
-        if (update(st, j.y, j.z, c)) { fl |= 2; break; }
-        snap = st;
-        lastr = r;
-        chunk_set(k, r, j.idx);
-        ++nh;
-        miss = 0;
-        if (h >= 0) {
-          h = nx.up;
-          if (h >= 0) {
-            nx = nn;
-            if (nx.up >= 0) nn = ws.chain[a + nx.up];
-          }
-        }
-      } else if (++miss > c.max_miss) {
-        break;
-      }
+    if (ei != kStepOk)
+      fl |= stop_flag(ei);
+    else
+      ok_init = true;
+  }
+  RowStage S;
+  S.pre_s = -1;
+  // seed chain (no gate), then outward following
+  bool live = ok_init;
+  int32_t h = c0.up;
+  int miss = 0;
+  const int r_first = kSync ? wave_min16(live ? r0 + 1 : R) : r0 + 1;
+  bool fetch = false;  // the chain record after nx is to be read
+  for (int r = r_first; r < R; ++r) {
+    bool staged = false;
+    if (kSync) {
+      if (!__ballot(live)) break;  // every lane's pass has ended
+      staged = stage_for(live && r > r0 && h < 0, live, s, r, r + 1, R, ws, stage, lane, S);
+    } else if (!live) {
+      break;
     }
-    chunk_store(k, rec);
-    // back to the start row without updates, then inward following; hits in
-    // the start row's chunk (already stored) are written singly, chunks below
-    // it are collected as outward
+    // read at the top of the step, after what the staging waits for: a read
+    // issued at the end of the previous step would be waited for here
+    if (fetch) {
+      nn = ws.chain[a + nx.up];
+      fetch = false;
+    }
+    if (!live || (kSync && r <= r0)) continue;  // ended, or waits for the wave's row
+    RowHdr hd;
+    if (!kSync && h < 0) hd = ws.hdr[(int64_t)s * R + r];  // issued before the transport arithmetic
+    ++w.n_prop;
+    const int e = propagate(st, row_x[r], c);
+    if (e) {
+      fl |= stop_flag(e);
+      live = false;
+      continue;
+    }
+    if ((r >> 3) != k.c) {
+      chunk_store(k, rec);
+      chunk_clear(k, r >> 3);
+      k_hi = r >> 3;
+    }
+    Pick j;
+    if (h >= 0) {
+      j.idx = h; j.y = nx.y; j.z = nx.z;
+    } else if (staged) {
+      stage_wait();
+      j = closest(st, staged_row_grid(S, stage), c, w);
+    } else {
+      if (kSync) hd = ws.hdr[(int64_t)s * R + r];
+      j = closest(st, grid_of(hd, ws), c, w);
+    }
+    if (j.idx >= 0) {
+      ++w.n_upd;
+      if (update(st, j.y, j.z, c)) {
+        fl |= 2;
+        live = false;
+        continue;
+      }
+      snap = st;
+      lastr = r;
+      chunk_set(k, r, j.idx);
+      ++nh;
+      miss = 0;
+      if (h >= 0) {
+        h = nx.up;
+        if (h >= 0) {
+          nx = nn;
+          fetch = nx.up >= 0;
+        }
+      }
+    } else if (++miss > c.max_miss) {
+      live = false;
+    }
+  }
+  if (in_range) chunk_store(k, rec);
+  // back to the start row without updates, then inward following; hits in
+  // the start row's chunk (already stored) are written singly, chunks below
+  // it are collected as outward
+  live = false;
+  if (ok_init) {
     st = snap;  // inward: snap becomes the state at the innermost update
     miss = 0;
     k.c = k0;
-    bool back_ok = true;
+    live = true;
     for (int r = lastr - 1; r >= r0; --r) {  // back to the start row, no updates
       ++w.n_prop;
       const int e = propagate(st, row_x[r], c);
-      if (e) { fl |= stop_flag(e); back_ok = false; break; }
-    }
-    if (back_ok) {
-      snap = st;
-      const int r_top = (kSync ? wave_max16(r0) : r0) - 1;
-      for (int r = r_top; r >= 0; --r) {
-        if (kSync && r >= r0) continue;  // waits for the wave's row
-        const RowHdr hd = ws.hdr[(int64_t)s * R + r];  // issued before the transport arithmetic
-        ++w.n_prop;
-        const int e = propagate(st, row_x[r], c);
-        if (e) { fl |= stop_flag(e); break; }
-        if ((r >> 3) != k.c) {
-          if (k.c < k0) chunk_store(k, rec);
-          chunk_clear(k, r >> 3);
-          k_lo = r >> 3;
-        }
-        const Pick j = closest(st, grid_of(hd, ws), c, w);
-        if (j.idx >= 0) {
-          ++w.n_upd;
-          if (update(st, j.y, j.z, c)) { fl |= 2; break; }
-          snap = st;
-          if (k.c == k0)
-            rec[r] = j.idx;
-          else
-            chunk_set(k, r, j.idx);
-          ++nh;
-          first_row = r;
-          miss = 0;
-        } else if (++miss > c.max_miss) {
-          break;
-        }
+      if (e) {
+        fl |= stop_flag(e);
+        live = false;
+        break;
       }
     }
-    if (k.c < k0) chunk_store(k, rec);
+    if (live) snap = st;
   }
+  const int r_top = (kSync ? wave_max16(live ? r0 : 0) : r0) - 1;
+  for (int r = r_top; r >= 0; --r) {
+    bool staged = false;
+    if (kSync) {
+      if (!__ballot(live)) break;  // every lane's pass has ended
+      staged = stage_for(live && r < r0, live, s, r, r - 1, R, ws, stage, lane, S);
+    } else if (!live) {
+      break;
+    }
+    if (!live || (kSync && r >= r0)) continue;  // ended, or waits for the wave's row
+    RowHdr hd;
+    if (!kSync) hd = ws.hdr[(int64_t)s * R + r];  // issued before the transport arithmetic
+    ++w.n_prop;
+    const int e = propagate(st, row_x[r], c);
+    if (e) {
+      fl |= stop_flag(e);
+      live = false;
+      continue;
+    }
+    if ((r >> 3) != k.c) {
+      if (k.c < k0) chunk_store(k, rec);
+      chunk_clear(k, r >> 3);
+      k_lo = r >> 3;
+    }
+    Pick j;
+    if (staged) {
+      stage_wait();
+      j = closest(st, staged_row_grid(S, stage), c, w);
+    } else {
+      if (kSync) hd = ws.hdr[(int64_t)s * R + r];
+      j = closest(st, grid_of(hd, ws), c, w);
+    }
+    if (j.idx >= 0) {
+      ++w.n_upd;
+      if (update(st, j.y, j.z, c)) {
+        fl |= 2;
+        live = false;
+        continue;
+      }
+      snap = st;
+      if (k.c == k0)
+        rec[r] = j.idx;
+      else
+        chunk_set(k, r, j.idx);
+      ++nh;
+      first_row = r;
+      miss = 0;
+    } else if (++miss > c.max_miss) {
+      live = false;
+    }
+  }
+  if (!in_range) return;
+  if (ok_init && k.c < k0) chunk_store(k, rec);
   // chunks the passes did not reach
   for (int q = 0; q < k_lo; ++q) chunk_store_none(q, rec);
   for (int q = k_hi + 1; q < RS / 8; ++q) chunk_store_none(q, rec);
@@ -1272,15 +1458,18 @@ __device__ __forceinline__ void build_tracklet(const Inputs& in, Span sp, int R,
 
 // kWaves > 0 asks the compiler to fit the kernel's registers for at least
 // kWaves resident waves per SIMD (spilling to scratch where needed).
+// Dynamic LDS: the pad-row planes (R floats, padded to 16 bytes), then, for
+// the row-synchronous form, kStageBytes per wave of the workgroup.
 template <int kWaves, bool kSync>
 __global__ __launch_bounds__(kTcMaxBlock) __attribute__((amdgpu_waves_per_eu(kWaves > 0 ? kWaves : 1))) void
 k_tracklets(Inputs in, Span sp, int R, const float* __restrict__ row_x, Consts c, Workspace ws, const int64_t* toff,
             int64_t first, int64_t cap, TrackletOut out, int nparts) {
   __shared__ int32_t chunk_lds[8 * kTcMaxBlock];
-  // the pad-row planes in LDS (dynamic, R floats): LDS reads do not wait
-  // behind the lane's outstanding memory loads as global reads would
+  // the pad-row planes in LDS: LDS reads do not wait behind the lane's
+  // outstanding memory loads as global reads would
   extern __shared__ __align__(16) unsigned char tc_dyn[];
   float* rxs = reinterpret_cast<float*>(tc_dyn);
+  unsigned char* stage = tc_dyn + tc_planes_bytes(R) + (threadIdx.x >> 6) * kStageBytes;
   for (int i = threadIdx.x; i < R; i += blockDim.x) rxs[i] = row_x[i];
   __syncthreads();
   const int64_t lo = max(toff[sp.s0], first);
@@ -1294,8 +1483,8 @@ k_tracklets(Inputs in, Span sp, int R, const float* __restrict__ row_x, Consts c
     const int64_t slot0 = take_slots(P, k, ws.counters + kCtrWork, 64, lane, pend);
     if (slot0 < 0) break;
     const int64_t slot = slot0 + lane;
-    if (slot < pend) build_tracklet<kSync>(in, sp, R, rxs, c, ws, toff, slot, slot - first, out, row_stride(R), chunk_lds,
-                                             w);
+    build_tracklet<kSync>(in, R, rxs, c, ws, slot, slot - first, slot < pend, out, row_stride(R), chunk_lds, stage,
+                          w);
   }
   flush_work(w, ws, lane);
 }
@@ -2452,16 +2641,15 @@ hipError_t launch_tracklets(const Inputs& in, Span sp, int n_rows, const float* 
                             const Workspace& ws, const int64_t* toff, int64_t first, int64_t cap,
                             const TrackletOut& out, int grid, int block, int nparts, int waves, int sync,
                             hipStream_t st) {
+  const size_t lds = (size_t)tc_planes_bytes(n_rows) + (sync ? (size_t)(block / 64) * kStageBytes : 0);
 #define CATPC_TC(K)                                                                                           \
   do {                                                                                                        \
     if (sync)                                                                                                 \
-      hipLaunchKernelGGL((k_tracklets<K, true>), dim3(grid), dim3(block), n_rows * sizeof(float), st, in, sp,     \
-                         n_rows, row_x, c, ws,                                                                \
+      hipLaunchKernelGGL((k_tracklets<K, true>), dim3(grid), dim3(block), lds, st, in, sp, n_rows, row_x, c, ws, \
                          toff, first, cap, out, nparts);                                                      \
     else                                                                                                      \
-      hipLaunchKernelGGL((k_tracklets<K, false>), dim3(grid), dim3(block), n_rows * sizeof(float), st, in, sp,    \
-                         n_rows, row_x, c, ws,                                                                \
-                         toff, first, cap, out, nparts);                                                      \
+      hipLaunchKernelGGL((k_tracklets<K, false>), dim3(grid), dim3(block), lds, st, in, sp, n_rows, row_x, c,    \
+                         ws, toff, first, cap, out, nparts);                                                  \
   } while (0)
   switch (waves) {
     case 5: CATPC_TC(5); break;
