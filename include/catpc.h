@@ -302,8 +302,10 @@ catpc_status catpc_stage_times(catpc_ctx* ctx, const catpc_input* in, const catp
 catpc_status catpc_work_counts(catpc_ctx* ctx, void* stream, int64_t* counts);
 
 /* Numerics probe: out[i] = a[i] OP b[i] on the device in binary32 for
- * op 0 '+', 1 '-', 2 '*', 3 '/', 4 sqrt(a[i]); device pointers, n elements.
- * Used to check that the device rounds like the host. */
+ * op 0 '+', 1 '-', 2 '*', 3 '/', 4 sqrt(a[i]), 5 the tracklet filter's
+ * shorter correctly rounded square root (valid for normal a[i] >= 2^-96; b
+ * unused for ops 4 and 5); device pointers, n elements.  Used to check that
+ * the device rounds like the host and that op 5 equals op 4 on its domain. */
 catpc_status catpc_fp32_probe(int32_t op, const float* a, const float* b, float* out, int64_t n, void* stream);
 
 /* Tracklet selection (Sec. 2 item 2: duplicate tracklets -- several seeds

@@ -804,7 +804,7 @@ catpc_status catpc_merge_counts(catpc_ctx* ctx, void* stream, int64_t* n_pairs, 
 }
 
 catpc_status catpc_fp32_probe(int32_t op, const float* a, const float* b, float* out, int64_t n, void* stream) {
-  if (op < 0 || op > 4 || n < 0 || (n > 0 && (!a || !b || !out))) return fail(CATPC_E_INVALID, "bad probe arguments");
+  if (op < 0 || op > 5 || n < 0 || (n > 0 && (!a || !b || !out))) return fail(CATPC_E_INVALID, "bad probe arguments");
   HIP_TRY(launch_fp32_probe(op, a, b, out, n, (hipStream_t)stream));
   return CATPC_OK;
 }

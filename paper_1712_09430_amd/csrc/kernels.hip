@@ -842,6 +842,25 @@ __device__ __forceinline__ int init_track(Trk& t, float x0, float y0, float z0, 
   return fabsf(t.s) < 0.999f ? kStepOk : kStepSinPhi;
 }
 
+// Correctly rounded square root for binary32 x that is normal, finite and at
+// least 2^-96: the hardware square root (within one ulp) and the choice
+// between it and its two neighbours by the signs of the fused residuals
+// x - s' s.  For such x these are the steps of the library's correctly
+// rounded sqrtf (its range scaling and its special-value fix-up do not
+// apply), so the result equals sqrtf(x) bit for bit; catpc_fp32_probe op 5
+// exposes it so that this is checked over every such x.  Used where
+// x = 1 - s^2 with |s| < 0.999, x in [0.001999, 1].
+__device__ __forceinline__ float sqrt_unit(float x) {
+  const float s = __builtin_amdgcn_sqrtf(x);
+  const float dn = __int_as_float(__float_as_int(s) - 1);
+  const float up = __int_as_float(__float_as_int(s) + 1);
+  const float r_dn = __builtin_fmaf(-dn, s, x);
+  const float r_up = __builtin_fmaf(-up, s, x);
+  float v = r_dn <= 0.0f ? dn : s;
+  v = r_up > 0.0f ? up : v;
+  return v;
+}
+
 // Helix transport to x1 (constant field): exact state transport, arc length
 // from the asin(u)/u series through u^8, covariance C <- J C J^T per block.
 __device__ __forceinline__ int propagate(Trk& t, float x1, const Consts& c) {
@@ -850,8 +869,9 @@ __device__ __forceinline__ int propagate(Trk& t, float x1, const Consts& c) {
   const float s0 = t.s;
   const float s1 = s0 + k * dx;
   if (!(fabsf(s1) < 0.999f)) return kStepSinPhi;
-  const float c0 = sqrtf(1.0f - s0 * s0);
-  const float c1 = sqrtf(1.0f - s1 * s1);
+  // |s0|, |s1| < 0.999 (every state the transport sees passed that check)
+  const float c0 = sqrt_unit(1.0f - s0 * s0);
+  const float c1 = sqrt_unit(1.0f - s1 * s1);
   const float T = (s0 + s1) / (c0 + c1);
   const float dy = dx * T;
   const float ch = sqrtf(dx * dx + dy * dy);
@@ -863,7 +883,7 @@ __device__ __forceinline__ int propagate(Trk& t, float x1, const Consts& c) {
   if (dx < 0.0f) dS = -dS;
   const float sm = (s0 + s1) * 0.5f;
   const float cm2 = 1.0f - sm * sm;
-  const float cm3 = cm2 * sqrtf(cm2);
+  const float cm3 = cm2 * sqrt_unit(cm2);
   const float a = dx / cm3;
   const float b = ((c.kb * dx) * dx * 0.5f) / cm3;
   const float d = c.kb * dx;
@@ -1152,17 +1172,19 @@ __device__ __forceinline__ int4 hdr_tail(const Workspace& ws, int64_t i) {
 // past it, inside the table's padding) and inside the row's hits.
 __device__ __forceinline__ void stage_row(int64_t i, int hit_base, int bin_half, int n, const StageLayout& L,
                                           const Workspace& ws, unsigned char* reg, int lane) {
-  if (lane == 0) __builtin_amdgcn_global_load_lds((GlobalPtr)(ws.hdr + i), (LdsPtr)reg, 16, 0, 0);
-  const int32_t* b0 = ws.bins + (2 * (int64_t)bin_half - L.off);
-  unsigned char* br = reg + 16;
-  for (int q = 0; q < L.bch; q += 64)
-    if (q + lane < L.bch)
-      __builtin_amdgcn_global_load_lds((GlobalPtr)(b0 + 4 * (q + lane)), (LdsPtr)(br + 16 * q), 16, 0, 0);
-  const SortedHit* h0 = ws.sorted + hit_base;
-  unsigned char* hr = br + 16 * L.bch;
-  for (int q = 0; q < n; q += 64)
-    if (q + lane < n)
-      __builtin_amdgcn_global_load_lds((GlobalPtr)(h0 + q + lane), (LdsPtr)(hr + 16 * q), 16, 0, 0);
+  // 16-byte chunk c of the copy: 0 the header's first half, 1 .. bch the bin
+  // table, then the hits
+  const uintptr_t hdr = reinterpret_cast<uintptr_t>(ws.hdr + i);
+  const uintptr_t bins = reinterpret_cast<uintptr_t>(ws.bins + (2 * (int64_t)bin_half - L.off));
+  const uintptr_t hits = reinterpret_cast<uintptr_t>(ws.sorted + hit_base);
+  const int total = 1 + L.bch + n;
+  for (int q = 0; q < total; q += 64) {
+    const int c = q + lane;
+    if (c < total) {
+      const uintptr_t src = c == 0 ? hdr : c <= L.bch ? bins + 16 * (uintptr_t)(c - 1) : hits + 16 * (uintptr_t)(c - 1 - L.bch);
+      __builtin_amdgcn_global_load_lds((GlobalPtr)src, (LdsPtr)(reg + 16 * q), 16, 0, 0);
+    }
+  }
 }
 
 // Wait for the wave's outstanding global memory operations (the LDS copies
@@ -2372,8 +2394,9 @@ __device__ __forceinline__ int prop_m(MTrk& t, float x1, float kb) {
   const float s0 = t.s;
   const float s1 = s0 + k * dx;
   if (!(fabsf(s1) < 0.999f)) return kStepSinPhi;
-  const float c0 = sqrtf(1.0f - s0 * s0);
-  const float c1 = sqrtf(1.0f - s1 * s1);
+  // |s0|, |s1| < 0.999 (every state the transport sees passed that check)
+  const float c0 = sqrt_unit(1.0f - s0 * s0);
+  const float c1 = sqrt_unit(1.0f - s1 * s1);
   const float T = (s0 + s1) / (c0 + c1);
   const float dy = dx * T;
   const float ch = sqrtf(dx * dx + dy * dy);
@@ -2385,7 +2408,7 @@ __device__ __forceinline__ int prop_m(MTrk& t, float x1, float kb) {
   if (dx < 0.0f) dS = -dS;
   const float sm = (s0 + s1) * 0.5f;
   const float cm2 = 1.0f - sm * sm;
-  const float cm3 = cm2 * sqrtf(cm2);
+  const float cm3 = cm2 * sqrt_unit(cm2);
   const double a = (double)(dx / cm3);
   const double b = (double)(((kb * dx) * dx * 0.5f) / cm3);
   const double d = (double)(kb * dx);
@@ -2517,7 +2540,8 @@ __global__ void k_fp32_probe(int op, const float* a, const float* b, float* o, i
     case 1: r = x - y; break;
     case 2: r = x * y; break;
     case 3: r = x / y; break;
-    default: r = sqrtf(x); break;
+    case 4: r = sqrtf(x); break;
+    default: r = sqrt_unit(x); break;
   }
   o[i] = r;
 }
