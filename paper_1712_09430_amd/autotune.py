@@ -45,6 +45,7 @@ SPACE = {
 
 # Serving: searched one coordinate at a time from the batch tuning.
 SERVE_SPACE = {
+    "tc_sync": [0, 1],
     "tc_xcd": [0, 1],
     "tc_waves_per_cu": [4, 6, 8, 12, 16],
     "tc_block": [64, 128, 256],
