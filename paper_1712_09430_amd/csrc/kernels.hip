@@ -1132,11 +1132,12 @@ __device__ __forceinline__ int wave_max16(int v) {
 }
 
 // LDS copy of one pad row's grid for a wave's searches (row-synchronous
-// form): the bin table from the 16-byte boundary at or below it, then the
-// row's sorted hits, copied straight from global memory into LDS
-// (global_load_lds, no registers) before the transport arithmetic, so the
-// search that follows the transport reads LDS instead of waiting on two
-// dependent global reads.  A row larger than kStageBytes is searched in place.
+// form): the header's bin origins, the bin table and the row's sorted hits,
+// copied straight from global memory into LDS (global_load_lds, no
+// registers; the workgroup size is a multiple of 64, so every wave is whole)
+// before the transport arithmetic, so the search that follows the transport
+// reads LDS instead of waiting on two dependent global reads.  A row larger
+// than kStageBytes is searched in place.
 constexpr int kStageBytes = 7168;  // per wave: rows of up to about 290 hits
 
 typedef __attribute__((address_space(1))) void* GlobalPtr;
