@@ -308,6 +308,20 @@ catpc_status catpc_work_counts(catpc_ctx* ctx, void* stream, int64_t* counts);
  * the device rounds like the host and that op 5 equals op 4 on its domain. */
 catpc_status catpc_fp32_probe(int32_t op, const float* a, const float* b, float* out, int64_t n, void* stream);
 
+/* Phase clocks of the row-synchronous tracklet kernel, for a profiling build
+ * of this library (kernels compiled with -DCATPC_PHASE_CLOCKS=1; in the
+ * product build every call returns CATPC_E_INVALID and the kernel records
+ * nothing).  The kernel sums shader-clock cycles over its waves, read by one
+ * lane at points every lane of the wave reaches.  out (host uint64[
+ * CATPC_PHASE_SLOTS]): [0] start of a slot batch (slots, chain records, seed
+ * state), [1] outward pass (seed chain and following), [2] record store and
+ * back-transport to the start row, [3] inward pass, [4] outward row steps,
+ * [5] inward row steps, [6] slot batches, [7] whole-wave cycles, [8] waves;
+ * summed since the last clear.  clear != 0: zero them (out unused).  The
+ * device must be idle. */
+#define CATPC_PHASE_SLOTS 9
+catpc_status catpc_phase_clocks(uint64_t* out, int32_t clear);
+
 /* Tracklet selection (Sec. 2 item 2: duplicate tracklets -- several seeds
  * that grew into the same segment -- are reduced to one per segment; Sec. 3:
  * this step follows the tracklet construction, many sectors per launch).

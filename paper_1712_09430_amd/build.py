@@ -21,20 +21,31 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=o
          "-Wall", "-Wno-unused-result"]
 
 
-def build(force: bool = True) -> str:
-    if not force and os.path.exists(LIB):
-        return LIB
+# Profiling build: the same sources with the tracklet kernel's phase clocks
+# compiled in (catpc_phase_clocks); used by phase_clocks.py, never by the
+# product path.
+PHASE_LIB = os.path.join(HERE, "libcatpc_phase.so")
+
+
+def build(force: bool = True, lib: str = LIB, defines=()) -> str:
+    if not force and os.path.exists(lib):
+        return lib
     with tempfile.TemporaryDirectory() as tmp:
         objs = []
         for src in SOURCES:
             o = os.path.join(tmp, src + ".o")
-            subprocess.run([HIPCC, *FLAGS, "-c", os.path.join(HERE, "csrc", src), "-o", o], check=True)
+            subprocess.run([HIPCC, *FLAGS, *defines, "-c", os.path.join(HERE, "csrc", src), "-o", o], check=True)
             objs.append(o)
-        out = LIB + ".tmp"
+        out = lib + ".tmp"
         subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", out], check=True)
-        os.replace(out, LIB)
-    return LIB
+        os.replace(out, lib)
+    return lib
+
+
+def build_phase_clocks(force: bool = True) -> str:
+    return build(force, PHASE_LIB, ("-DCATPC_PHASE_CLOCKS=1",))
 
 
 if __name__ == "__main__":
     print(build())
+    print(build_phase_clocks())

@@ -24,7 +24,7 @@ STAGES = ("row_index", "grid", "neighbours", "clean_start", "scan", "compact", "
 
 EXPORTS = ("catpc_track_batch_noalloc", "catpc_sector_frame", "catpc_to_global", "catpc_stage_times", "catpc_work_counts", "catpc_default_params", "catpc_default_tuning", "catpc_row_stride", "catpc_workspace_bytes", "catpc_create", "catpc_destroy",
            "catpc_set_params", "catpc_set_tuning", "catpc_get_tuning", "catpc_track_batch", "catpc_track_plain",
-           "catpc_result", "catpc_fetch_tracklets", "catpc_select_tracklets", "catpc_select_result", "catpc_refit_tracks", "catpc_default_merge_params", "catpc_merge_tracks", "catpc_merge_counts", "catpc_fp32_probe", "catpc_probe_copy", "catpc_probe_fma",
+           "catpc_result", "catpc_fetch_tracklets", "catpc_select_tracklets", "catpc_select_result", "catpc_refit_tracks", "catpc_default_merge_params", "catpc_merge_tracks", "catpc_merge_counts", "catpc_fp32_probe", "catpc_phase_clocks", "catpc_probe_copy", "catpc_probe_fma",
            "catpc_last_error")
 
 
@@ -149,6 +149,8 @@ def lib():
         L.catpc_work_counts.restype = st
         L.catpc_fp32_probe.argtypes = [ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int64, _vp]
         L.catpc_fp32_probe.restype = st
+        L.catpc_phase_clocks.argtypes = [P(ctypes.c_uint64), ctypes.c_int32]
+        L.catpc_phase_clocks.restype = st
         L.catpc_probe_copy.argtypes = [_vp, _vp, ctypes.c_int64, _vp]
         L.catpc_probe_copy.restype = st
         L.catpc_probe_fma.argtypes = [_vp, ctypes.c_int64, ctypes.c_int32, _vp]
@@ -320,6 +322,17 @@ def catpc_work_counts(ctx, stream):
 
 def catpc_fp32_probe(op, a, b, out, n, stream):
     return _check(lib().catpc_fp32_probe(int(op), a, b, out, int(n), stream))
+
+
+PHASE_SLOTS = 9
+
+
+def catpc_phase_clocks(clear=False):
+    """Phase clocks of a profiling build (see include/catpc.h); a list of
+    PHASE_SLOTS ints, or None after a clear."""
+    buf = (ctypes.c_uint64 * PHASE_SLOTS)()
+    _check(lib().catpc_phase_clocks(buf, 1 if clear else 0))
+    return None if clear else [int(v) for v in buf]
 
 
 def catpc_probe_copy(src, dst, n_bytes, stream):

@@ -803,6 +803,14 @@ catpc_status catpc_merge_counts(catpc_ctx* ctx, void* stream, int64_t* n_pairs, 
   return CATPC_OK;
 }
 
+catpc_status catpc_phase_clocks(uint64_t* out, int32_t clear) {
+  if (!clear && !out) return fail(CATPC_E_INVALID, "NULL argument");
+  const hipError_t e = phase_clocks(reinterpret_cast<unsigned long long*>(out), clear != 0);
+  if (e == hipErrorNotSupported) return fail(CATPC_E_INVALID, "not a profiling build (-DCATPC_PHASE_CLOCKS=1)");
+  HIP_TRY(e);
+  return CATPC_OK;
+}
+
 catpc_status catpc_fp32_probe(int32_t op, const float* a, const float* b, float* out, int64_t n, void* stream) {
   if (op < 0 || op > 5 || n < 0 || (n > 0 && (!a || !b || !out))) return fail(CATPC_E_INVALID, "bad probe arguments");
   HIP_TRY(launch_fp32_probe(op, a, b, out, n, (hipStream_t)stream));

@@ -204,4 +204,13 @@ hipError_t launch_probe_copy(const void* src, void* dst, int64_t n16, hipStream_
 hipError_t launch_probe_fma(float* out, int64_t n, int iters, hipStream_t st);
 hipError_t launch_fp32_probe(int op, const float* a, const float* b, float* out, int64_t n, hipStream_t st);
 
+// Phase clocks of the row-synchronous tracklet kernel (profiling build,
+// -DCATPC_PHASE_CLOCKS=1): cycles summed over slot batches of each phase,
+// row steps of the two passes, slot batches, and whole-wave cycles and waves.
+enum {
+  kPhaseStart, kPhaseOut, kPhaseBack, kPhaseIn, kPhaseOutSteps, kPhaseInSteps, kPhaseBatches, kPhaseWave, kPhaseWaves,
+  kPhaseSlots
+};
+hipError_t phase_clocks(unsigned long long* out, bool clear);  // hipErrorNotSupported outside the profiling build
+
 }  // namespace catpc

@@ -1257,6 +1257,21 @@ __device__ __forceinline__ bool stage_for(bool want, bool live, int s, int r, in
   return mine;
 }
 
+// Profiling build only (-DCATPC_PHASE_CLOCKS=1): shader-clock cycles of the
+// row-synchronous tracklet kernel's phases, summed over waves by lane 0 at
+// points every lane of the wave reaches (see kPhaseSlots for the layout).  In
+// the product build phase_clock() is the constant 0 and nothing is recorded.
+#ifndef CATPC_PHASE_CLOCKS
+#define CATPC_PHASE_CLOCKS 0
+#endif
+constexpr bool kPhaseClocks = CATPC_PHASE_CLOCKS != 0;
+__device__ unsigned long long g_phase_clocks[kPhaseSlots];
+
+__device__ __forceinline__ unsigned long long phase_clock() {
+  if constexpr (kPhaseClocks) return (unsigned long long)clock64();
+  return 0ull;
+}
+
 // One tracklet: slot -> start hit -> seed chain -> following -> output.
 // Every lane of the wave calls it (`valid`: the lane has a slot).  kSync: the
 // lanes of a wave walk the pad rows together (a lane whose pass starts later
@@ -1269,6 +1284,8 @@ __device__ __forceinline__ void build_tracklet(const Inputs& in, int R, const fl
                                                const TrackletOut& out, int RS, int32_t* chunk_lds,
                                                unsigned char* stage, Work& w) {
   const int lane = threadIdx.x & 63;
+  const unsigned long long t_start = phase_clock();
+  unsigned n_out = 0, n_in = 0;  // row steps of the two passes (profiling build)
   int s = 0, r0 = 0;
   int64_t a = 0, gi = 0;
   if (valid) {
@@ -1329,8 +1346,10 @@ __device__ __forceinline__ void build_tracklet(const Inputs& in, int R, const fl
   int32_t h = c0.up;
   int miss = 0;
   const int r_first = kSync ? wave_min16(live ? r0 + 1 : R) : r0 + 1;
+  const unsigned long long t_out = phase_clock();
   bool fetch = false;  // the chain record after nx is to be read
   for (int r = r_first; r < R; ++r) {
+    if (kPhaseClocks) ++n_out;
     bool staged = false;
     if (kSync) {
       if (!__ballot(live)) break;  // every lane's pass has ended
@@ -1392,6 +1411,7 @@ __device__ __forceinline__ void build_tracklet(const Inputs& in, int R, const fl
       live = false;
     }
   }
+  const unsigned long long t_back = phase_clock();
   if (in_range) chunk_store(k, rec);
   // back to the start row without updates, then inward following; hits in
   // the start row's chunk (already stored) are written singly, chunks below
@@ -1414,7 +1434,9 @@ __device__ __forceinline__ void build_tracklet(const Inputs& in, int R, const fl
     if (live) snap = st;
   }
   const int r_top = (kSync ? wave_max16(live ? r0 : 0) : r0) - 1;
+  const unsigned long long t_in = phase_clock();
   for (int r = r_top; r >= 0; --r) {
+    if (kPhaseClocks) ++n_in;
     bool staged = false;
     if (kSync) {
       if (!__ballot(live)) break;  // every lane's pass has ended
@@ -1464,6 +1486,18 @@ __device__ __forceinline__ void build_tracklet(const Inputs& in, int R, const fl
       live = false;
     }
   }
+  if constexpr (kPhaseClocks && kSync) {
+    if (lane == 0) {
+      const unsigned long long t_end = phase_clock();
+      atomicAdd(&g_phase_clocks[kPhaseStart], t_out - t_start);
+      atomicAdd(&g_phase_clocks[kPhaseOut], t_back - t_out);
+      atomicAdd(&g_phase_clocks[kPhaseBack], t_in - t_back);
+      atomicAdd(&g_phase_clocks[kPhaseIn], t_end - t_in);
+      atomicAdd(&g_phase_clocks[kPhaseOutSteps], (unsigned long long)n_out);
+      atomicAdd(&g_phase_clocks[kPhaseInSteps], (unsigned long long)n_in);
+      atomicAdd(&g_phase_clocks[kPhaseBatches], 1ull);
+    }
+  }
   if (!in_range) return;
   if (ok_init && k.c < k0) chunk_store(k, rec);
   // chunks the passes did not reach
@@ -1501,6 +1535,7 @@ k_tracklets(Inputs in, Span sp, int R, const float* __restrict__ row_x, Consts c
   Work w = {0, 0, 0, 0};
   const Parts P = make_parts(lo, hi, nparts);
   int k = 0;
+  const unsigned long long t_wave = phase_clock();
   while (true) {
     int64_t pend = 0;
     const int64_t slot0 = take_slots(P, k, ws.counters + kCtrWork, 64, lane, pend);
@@ -1508,6 +1543,12 @@ k_tracklets(Inputs in, Span sp, int R, const float* __restrict__ row_x, Consts c
     const int64_t slot = slot0 + lane;
     build_tracklet<kSync>(in, R, rxs, c, ws, slot, slot - first, slot < pend, out, row_stride(R), chunk_lds, stage,
                           w);
+  }
+  if constexpr (kPhaseClocks && kSync) {
+    if (lane == 0) {
+      atomicAdd(&g_phase_clocks[kPhaseWave], phase_clock() - t_wave);
+      atomicAdd(&g_phase_clocks[kPhaseWaves], 1ull);
+    }
   }
   flush_work(w, ws, lane);
 }
@@ -2748,6 +2789,15 @@ hipError_t launch_probe_fma(float* out, int64_t n, int iters, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_probe_fma, dim3(blocks_for(n, 256)), dim3(256), 0, st, out, n, iters);
   return hipGetLastError();
+}
+
+hipError_t phase_clocks(unsigned long long* out, bool clear) {
+  if (!kPhaseClocks) return hipErrorNotSupported;
+  if (clear) {
+    const unsigned long long z[kPhaseSlots] = {};
+    return hipMemcpyToSymbol(HIP_SYMBOL(g_phase_clocks), z, sizeof(z));
+  }
+  return hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase_clocks), sizeof(unsigned long long) * kPhaseSlots);
 }
 
 hipError_t launch_fp32_probe(int op, const float* a, const float* b, float* out, int64_t n, hipStream_t st) {

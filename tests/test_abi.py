@@ -65,6 +65,9 @@ def test_host_validation(lib):
     assert lib.catpc_track_batch(None, None, None, None) == C.CATPC_E_INVALID
     assert lib.catpc_result(None, None, None) == C.CATPC_E_INVALID
     assert lib.catpc_fp32_probe(7, None, None, None, 1, None) == C.CATPC_E_INVALID
+    # the product build records no phase clocks (only the profiling build does)
+    assert lib.catpc_phase_clocks(None, 1) == C.CATPC_E_INVALID
+    assert "profiling build" in C.catpc_last_error()
 
 
 def test_row_stride(lib):
