@@ -89,6 +89,15 @@ class catpc_tracks(ctypes.Structure):
 _lib = None
 
 
+def use_library(path):
+    """Bind the functions below to another build of the library (the
+    profiling build, `build.PHASE_LIB`); the next call loads it.  Contexts
+    made with the previous library must be destroyed first."""
+    global _lib, LIB_PATH
+    LIB_PATH = path
+    _lib = None
+
+
 def lib():
     """Load libcatpc.so; raises if it is not built."""
     global _lib

@@ -47,8 +47,7 @@ def main():
     tr.result()
     product_ms = stage_ms(tr, hits, out)
     tr.close()
-    C.LIB_PATH = build.PHASE_LIB
-    C._lib = None
+    C.use_library(build.PHASE_LIB)
     tr = Tracker(b.row_x, hits.n_hits, hits.n_sectors, tuning=tuning, device="cuda:0")
     out = tr.output(hits)
     tr.track(hits, out)
