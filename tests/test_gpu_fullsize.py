@@ -3,12 +3,12 @@
 
 - the full event (10k tracks, 36 sectors, ~1.75 M hits): every sector checked
   against the oracle, bit for bit;
-- the 64-event batch (2304 uneven sectors, ~22 M hits): a sample of sectors
-  (the largest, the smallest non-empty, and seeded random ones) checked
-  against the oracle one by one, bit for bit, plus properties that hold at any
-  size for every sector (links climb one row, at most one incoming link,
-  per-sector tracklet counts equal the start-hit counts, every tracklet lists
-  its start hit and only hits of its own sector)."""
+- the 64-event batch (2304 uneven sectors, ~22 M hits, 379 570 tracklets):
+  every sector checked against the oracle, bit for bit (the oracle runs on a
+  thread pool, ~10 s), plus properties that hold at any size (links climb one
+  row, at most one incoming link, per-sector tracklet counts equal the
+  start-hit counts, every tracklet lists its start hit and only hits of its
+  own sector)."""
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
@@ -48,7 +48,7 @@ def check_sectors(batch, out, n, params, sectors):
     def one(s):
         return compare_sector(batch, s, gpu_sector(batch, out, links, trk, s), params)
 
-    with ThreadPoolExecutor(max_workers=8) as ex:
+    with ThreadPoolExecutor(max_workers=16) as ex:
         bad = [m for r in ex.map(one, sectors) for m in r]
     assert not bad, "\n".join(bad[:20])
     return links, trk
@@ -60,16 +60,11 @@ def test_full_event_every_sector_bit_exact():
     check_sectors(b, out, n, p, range(b.n_sectors))
 
 
-def test_batch64_sampled_sectors_bit_exact_and_global_properties():
+def test_batch64_every_sector_bit_exact_and_global_properties():
     b = synth.batch_workload(seed=1, n_events=64)
     tr, hits, out, n, p = run_bench_config(b)
     sizes = np.diff(b.hit_offset)
-    order = np.argsort(sizes, kind="stable")
-    nonempty = order[sizes[order] > 0]
-    rng = np.random.default_rng(2024)
-    sample = sorted(set(order[-6:].tolist()) | set(nonempty[:6].tolist()) |
-                    set(rng.choice(b.n_sectors, 24, replace=False).tolist()))
-    links, trk = check_sectors(b, out, n, p, sample)
+    links, trk = check_sectors(b, out, n, p, range(b.n_sectors))
     # properties over every sector
     up, off = links["link_up"], links["tracklet_offset"]
     assert off[0] == 0 and np.all(np.diff(off) >= 0) and off[-1] == n
@@ -92,10 +87,10 @@ def test_batch64_sampled_sectors_bit_exact_and_global_properties():
     assert np.array_equal((rh >= 0).sum(1), trk["n_hits"])
 
 
-def test_batch64_refit_and_merge_sampled_sectors_bit_exact():
+def test_batch64_refit_and_merge_every_sector_bit_exact():
     """Selection, refit and segment merging after the bench configuration's
-    track call on the 64-event batch: the fits and the links of sampled
-    sectors against the oracle."""
+    track call on the 64-event batch: the fits and the links of every sector
+    against the oracle (~35 s of oracle work on a thread pool)."""
     from _harness import chains, oracle_merge_sector, oracle_params
     from test_gpu_refit import compare_sector_fits
     b = synth.batch_workload(seed=1, n_events=64)
@@ -110,8 +105,7 @@ def test_batch64_refit_and_merge_sampled_sectors_bit_exact():
     torch.cuda.synchronize()
     g, m, f = tracks.numpy(nt, nh), merges.numpy(nt), fits.numpy(nt)
     sizes = np.diff(b.hit_offset)
-    rng = np.random.default_rng(77)
-    sample = sorted(set(np.argsort(sizes)[-2:].tolist()) | set(rng.choice(b.n_sectors, 8, replace=False).tolist()))
+    sample = range(b.n_sectors)
     P = oracle_params(p)
 
     def one(s):
@@ -132,6 +126,6 @@ def test_batch64_refit_and_merge_sampled_sectors_bit_exact():
             bad.append(f"sector {s}: chi2")
         return bad
 
-    with ThreadPoolExecutor(max_workers=8) as ex:
+    with ThreadPoolExecutor(max_workers=16) as ex:
         bad = [x for r in ex.map(one, sample) for x in r]
     assert not bad, "\n".join(bad)
