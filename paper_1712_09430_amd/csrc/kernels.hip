@@ -1065,8 +1065,9 @@ __device__ __forceinline__ void flush_work(const Work& w, const Workspace& ws, i
   }
 }
 
-// Slot partitions of the persistent tracklet kernels.  With nparts == kXcds
-// the slot range is cut into kXcds contiguous parts and a workgroup starts on
+// Work partitions of the persistent tracklet kernel (a range of tracklet
+// batches).  With nparts == kXcds the range is cut into kXcds contiguous
+// parts and a workgroup starts on
 // the part of the die it runs on (workgroups are dispatched round-robin over
 // the dies), so the row grids a die's L2 holds belong to fewer sectors; a
 // wave whose part is used up continues with the following parts.
@@ -1085,9 +1086,9 @@ __device__ __forceinline__ Parts make_parts(int64_t lo, int64_t hi, int nparts) 
   return P;
 }
 
-// Wave-uniform: take `want` consecutive slots from the current part (index k,
-// advanced past used-up parts).  Returns the first slot and the part's end,
-// or -1 when every part is used up.
+// Wave-uniform: take `want` consecutive items (batches) from the current part
+// (index k, advanced past used-up parts).  Returns the first item and the
+// part's end, or -1 when every part is used up.
 __device__ __forceinline__ int64_t take_slots(const Parts& P, int& k, unsigned long long* ctr, int want, int lane,
                                               int64_t& part_end) {
   while (k < P.nparts) {
@@ -1513,6 +1514,50 @@ __device__ __forceinline__ void build_tracklet(const Inputs& in, int R, const fl
   out.flags[o] = fl;
 }
 
+// Tracklet batches: 64 consecutive slots of one sector (a sector's last batch
+// may hold fewer), so that a wave's lanes always search the rows of one
+// sector and the row copy serves every one of them.  batch_off[i] = first
+// batch of sector s0 + i, i in [0, S]: the exclusive prefix sum of
+// ceil(tracklets / 64) over the span's sectors (one workgroup of 1024).
+__global__ __launch_bounds__(1024) void k_batches(const int64_t* __restrict__ toff, int s0, int s1,
+                                                  int32_t* __restrict__ batch_off) {
+  __shared__ int wsum[16];
+  const int S = s1 - s0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int carry = 0;
+  for (int base = 0; base < S; base += 1024) {
+    const int i = base + (int)threadIdx.x;
+    const int v = i < S ? (int)((toff[s0 + i + 1] - toff[s0 + i] + 63) >> 6) : 0;
+    int incl = v;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int u = __shfl_up(incl, d);
+      if (lane >= d) incl += u;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int before = carry;
+    for (int q = 0; q < wv; ++q) before += wsum[q];
+    if (i < S) batch_off[i] = before + incl - v;
+    int total = 0;
+    for (int q = 0; q < 16; ++q) total += wsum[q];
+    carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) batch_off[S] = carry;
+}
+
+// Largest i in [0, n) with off[i] <= v (off non-decreasing, off[0] <= v);
+// wave-uniform v, so every lane reads the same entries.
+template <class T>
+__device__ __forceinline__ int last_le(const T* off, int n, int64_t v) {
+  int a = 0, b = n;  // off[a] <= v, and off[b] > v or b == n
+  while (b - a > 1) {
+    const int m = (a + b) >> 1;
+    if ((int64_t)off[m] <= v) a = m; else b = m;
+  }
+  return a;
+}
+
 // kWaves > 0 asks the compiler to fit the kernel's registers for at least
 // kWaves resident waves per SIMD (spilling to scratch where needed).
 // Dynamic LDS: the pad-row planes (R floats, padded to 16 bytes), then, for
@@ -1529,20 +1574,32 @@ k_tracklets(Inputs in, Span sp, int R, const float* __restrict__ row_x, Consts c
   unsigned char* stage = tc_dyn + tc_planes_bytes(R) + (threadIdx.x >> 6) * kStageBytes;
   for (int i = threadIdx.x; i < R; i += blockDim.x) rxs[i] = row_x[i];
   __syncthreads();
+  // slots [lo, hi) are tracked; the work queue hands out the batches that
+  // cover them
   const int64_t lo = max(toff[sp.s0], first);
   const int64_t hi = min(toff[sp.s1], first + cap);
+  const int S = sp.s1 - sp.s0;
   const int lane = threadIdx.x & 63;
   Work w = {0, 0, 0, 0};
-  const Parts P = make_parts(lo, hi, nparts);
+  int64_t blo = 0, bhi = 0;
+  if (lo < hi) {
+    const int i0 = last_le(toff + sp.s0, S, lo), i1 = last_le(toff + sp.s0, S, hi - 1);
+    blo = ws.batch_off[i0] + (lo - toff[sp.s0 + i0]) / 64;
+    bhi = ws.batch_off[i1] + (hi - 1 - toff[sp.s0 + i1]) / 64 + 1;
+  }
+  const Parts P = make_parts(blo, bhi, nparts);
   int k = 0;
   const unsigned long long t_wave = phase_clock();
   while (true) {
     int64_t pend = 0;
-    const int64_t slot0 = take_slots(P, k, ws.counters + kCtrWork, 64, lane, pend);
-    if (slot0 < 0) break;
+    const int64_t b = take_slots(P, k, ws.counters + kCtrWork, 1, lane, pend);
+    if (b < 0) break;
+    const int i = last_le(ws.batch_off, S, b);
+    const int64_t slot0 = toff[sp.s0 + i] + 64 * (b - ws.batch_off[i]);
+    const int64_t send = min(toff[sp.s0 + i + 1], slot0 + 64);
     const int64_t slot = slot0 + lane;
-    build_tracklet<kSync>(in, R, rxs, c, ws, slot, slot - first, slot < pend, out, row_stride(R), chunk_lds, stage,
-                          w);
+    build_tracklet<kSync>(in, R, rxs, c, ws, slot, slot - first, slot < send && slot >= lo && slot < hi, out,
+                          row_stride(R), chunk_lds, stage, w);
   }
   if constexpr (kPhaseClocks && kSync) {
     if (lane == 0) {
@@ -2707,6 +2764,9 @@ hipError_t launch_tracklets(const Inputs& in, Span sp, int n_rows, const float* 
                             const Workspace& ws, const int64_t* toff, int64_t first, int64_t cap,
                             const TrackletOut& out, int grid, int block, int nparts, int waves, int sync,
                             hipStream_t st) {
+  const int S = sp.s1 - sp.s0;
+  if (S <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batches, dim3(1), dim3(1024), 0, st, toff, sp.s0, sp.s1, ws.batch_off);
   const size_t lds = (size_t)tc_planes_bytes(n_rows) + (sync ? (size_t)(block / 64) * kStageBytes : 0);
 #define CATPC_TC(K)                                                                                           \
   do {                                                                                                        \
