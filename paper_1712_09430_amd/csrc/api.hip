@@ -39,8 +39,8 @@ catpc_status hip_fail(hipError_t e, const char* what) {
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t row_first, hdr, bins, sorted, raw_up, raw_dn, mask, blk_sec, blk_cnt, blk_off, grp_off, start_glob, start_sec,
-      batch_off, chain,
+  size_t row_first, hdr, bins, sorted, raw_up, raw_dn, mask, blk_sec, blk_cnt, blk_off, grp_off, start_glob, batch_off,
+      chain,
       owner, sel_cnt, sel_local, sel_loc, sel_grp, sel_mask, mrec, mkey_a, mkey_b, mpair, mover, mslot, mchunk, counters;
   size_t total;
 };
@@ -64,7 +64,6 @@ Layout plan(int32_t R, int64_t H, int32_t S, bool hot_only = false) {
   L.blk_off = take(sizeof(int64_t) * (nblk + 8));
   L.grp_off = take(sizeof(int64_t) * (nblk / 1024 + 8));
   L.start_glob = take(sizeof(int32_t) * (size_t)(H + 1));
-  L.start_sec = take(sizeof(int32_t) * (size_t)(H + 1));
   L.batch_off = take(sizeof(int32_t) * ((size_t)S + 2));
   L.chain = take(sizeof(ChainHit) * (size_t)(H + 1));
   const size_t slots = hot_only ? 0 : (size_t)(H / 3) + 2;  // tracklets <= H/3: seeds are disjoint chains of >= 3 hits
@@ -101,7 +100,6 @@ Workspace carve(char* b, const Layout& L) {
   w.blk_off = (int64_t*)(b + L.blk_off);
   w.grp_off = (int64_t*)(b + L.grp_off);
   w.start_glob = (int32_t*)(b + L.start_glob);
-  w.start_sec = (int32_t*)(b + L.start_sec);
   w.batch_off = (int32_t*)(b + L.batch_off);
   w.chain = (ChainHit*)(b + L.chain);
   w.owner = (unsigned*)(b + L.owner);

@@ -63,7 +63,6 @@ struct Workspace {
   int64_t* blk_off;      // [H/256 + 8] first slot of each block, relative to its group of 1024 blocks
   int64_t* grp_off;      // [H/256/1024 + 8] first slot of each group of 1024 blocks
   int32_t* start_glob;   // [H] global hit index of each tracklet slot
-  int32_t* start_sec;    // [H] sector of each tracklet slot
   int32_t* batch_off;    // [S + 1] first tracklet batch of each sector (64 slots of one sector per batch)
   ChainHit* chain;       // [H] coordinates + cleaned up-link per hit (input order)
   unsigned* owner;               // [H] tracklet selection: weight of the tracklet that keeps each hit (row chunks too dense for LDS)

@@ -801,7 +801,6 @@ __global__ __launch_bounds__(kHitsPerBlock) void k_compact(Inputs in, Span sp, i
         while (s + 1 < sp.s1 && in.hit_offset[s + 1] <= i) ++s;
         start_hit[pos] = (int32_t)(i - in.hit_offset[s]);
         ws.start_glob[pos] = (int32_t)i;
-        ws.start_sec[pos] = s;
         ++pos;
         m &= m - 1ull;
       } while (m);
@@ -1220,20 +1219,18 @@ __device__ __forceinline__ RowGrid staged_row_grid(const RowStage& S, unsigned c
 }
 
 // At the top of a row step, every lane of the wave active: stage row r of the
-// sector of the wave's first lane that searches there (`want`), when it fits,
-// and read ahead the header of row rnext.  Returns whether this lane's search
-// uses the copy.
-__device__ __forceinline__ bool stage_for(bool want, bool live, int s, int r, int rnext, int R, const Workspace& ws,
+// wave's sector s (wave-uniform: a batch holds slots of one sector) when a
+// lane searches there (`want`) and the copy fits, and read ahead the header of
+// row rnext.  Returns whether this lane's search uses the copy.
+__device__ __forceinline__ bool stage_for(bool want, int s, int r, int rnext, int R, const Workspace& ws,
                                           unsigned char* reg, int lane, RowStage& S) {
   const unsigned long long m = __ballot(want);
-  const unsigned long long lv = __ballot(live);
-  const unsigned long long pick = m ? m : lv;
-  const int sw = __builtin_amdgcn_readlane(s, __ffsll((long long)pick) - 1);
+  const int su = __builtin_amdgcn_readfirstlane(s);
   const int ru = __builtin_amdgcn_readfirstlane(r);
   bool mine = false;
   if (m) {
-    const int64_t i = (int64_t)sw * R + ru;
-    const int4 t = (sw == S.pre_s && ru == S.pre_r) ? S.pre : hdr_tail(ws, i);
+    const int64_t i = (int64_t)su * R + ru;
+    const int4 t = (su == S.pre_s && ru == S.pre_r) ? S.pre : hdr_tail(ws, i);
     const int nyz = __builtin_amdgcn_readfirstlane(t.x);
     S.ny = (int16_t)(nyz & 0xffff);
     S.nz = (int16_t)(nyz >> 16);
@@ -1244,15 +1241,15 @@ __device__ __forceinline__ bool stage_for(bool want, bool live, int s, int r, in
       S.L = stage_layout(S.ny, S.nz, bin_half, n);
       if (S.L.bytes <= kStageBytes) {
         stage_row(i, hit_base, bin_half, n, S.L, ws, reg, lane);
-        mine = want && s == sw;
+        mine = want;
       }
     }
   }
   const int rn = __builtin_amdgcn_readfirstlane(rnext);
   S.pre_s = -1;
   if (rn >= 0 && rn < R) {
-    S.pre = hdr_tail(ws, (int64_t)sw * R + rn);
-    S.pre_s = sw;
+    S.pre = hdr_tail(ws, (int64_t)su * R + rn);
+    S.pre_s = su;
     S.pre_r = rn;
   }
   return mine;
@@ -1274,24 +1271,25 @@ __device__ __forceinline__ unsigned long long phase_clock() {
 }
 
 // One tracklet: slot -> start hit -> seed chain -> following -> output.
-// Every lane of the wave calls it (`valid`: the lane has a slot).  kSync: the
+// Every lane of the wave calls it (`valid`: the lane has a slot; `sector`:
+// the sector of the wave's batch).  kSync: the
 // lanes of a wave walk the pad rows together (a lane whose pass starts later
-// waits, a lane whose pass has ended idles), and the row every searching lane
-// of one sector needs is staged in LDS (`stage`, kStageBytes, this wave's);
+// waits, a lane whose pass has ended idles), and the row the searching lanes
+// need is staged in LDS (`stage`, kStageBytes, this wave's);
 // each lane's own sequence of filter steps is the same either way.
 template <bool kSync>
 __device__ __forceinline__ void build_tracklet(const Inputs& in, int R, const float* __restrict__ row_x, const Consts& c,
-                                               const Workspace& ws, int64_t slot, int64_t o, bool valid,
-                                               const TrackletOut& out, int RS, int32_t* chunk_lds,
+                                               const Workspace& ws, int sector, int64_t slot, int64_t o,
+                                               bool valid, const TrackletOut& out, int RS, int32_t* chunk_lds,
                                                unsigned char* stage, Work& w) {
   const int lane = threadIdx.x & 63;
   const unsigned long long t_start = phase_clock();
   unsigned n_out = 0, n_in = 0;  // row steps of the two passes (profiling build)
-  int s = 0, r0 = 0;
-  int64_t a = 0, gi = 0;
+  const int s = sector;
+  const int64_t a = in.hit_offset[s];
+  int r0 = 0;
+  int64_t gi = a;
   if (valid) {
-    s = ws.start_sec[slot];
-    a = in.hit_offset[s];
     gi = ws.start_glob[slot];
     r0 = in.row[gi];
   }
@@ -1354,7 +1352,7 @@ __device__ __forceinline__ void build_tracklet(const Inputs& in, int R, const fl
     bool staged = false;
     if (kSync) {
       if (!__ballot(live)) break;  // every lane's pass has ended
-      staged = stage_for(live && r > r0 && h < 0, live, s, r, r + 1, R, ws, stage, lane, S);
+      staged = stage_for(live && r > r0 && h < 0, s, r, r + 1, R, ws, stage, lane, S);
     } else if (!live) {
       break;
     }
@@ -1441,7 +1439,7 @@ __device__ __forceinline__ void build_tracklet(const Inputs& in, int R, const fl
     bool staged = false;
     if (kSync) {
       if (!__ballot(live)) break;  // every lane's pass has ended
-      staged = stage_for(live && r < r0, live, s, r, r - 1, R, ws, stage, lane, S);
+      staged = stage_for(live && r < r0, s, r, r - 1, R, ws, stage, lane, S);
     } else if (!live) {
       break;
     }
@@ -1598,8 +1596,8 @@ k_tracklets(Inputs in, Span sp, int R, const float* __restrict__ row_x, Consts c
     const int64_t slot0 = toff[sp.s0 + i] + 64 * (b - ws.batch_off[i]);
     const int64_t send = min(toff[sp.s0 + i + 1], slot0 + 64);
     const int64_t slot = slot0 + lane;
-    build_tracklet<kSync>(in, R, rxs, c, ws, slot, slot - first, slot < send && slot >= lo && slot < hi, out,
-                          row_stride(R), chunk_lds, stage, w);
+    build_tracklet<kSync>(in, R, rxs, c, ws, sp.s0 + i, slot, slot - first, slot < send && slot >= lo && slot < hi,
+                          out, row_stride(R), chunk_lds, stage, w);
   }
   if constexpr (kPhaseClocks && kSync) {
     if (lane == 0) {
