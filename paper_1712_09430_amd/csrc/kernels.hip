@@ -295,6 +295,20 @@ __global__ __launch_bounds__(64) void k_grid(Inputs in, Span sp, int R, float bi
   }
 }
 
+// Global-to-LDS copies (global_load_lds): lane j of a copy instruction writes
+// entry j of its (wave-uniform) LDS destination; nothing orders a later LDS
+// read after them but a wait for the wave's memory operations.
+typedef __attribute__((address_space(1))) void* GlobalPtr;
+typedef __attribute__((address_space(3))) void* LdsPtr;
+
+// Wait for the wave's outstanding global memory operations (the LDS copies
+// among them: nothing else orders a later LDS read after them).
+__device__ __forceinline__ void stage_wait() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), other counters not waited
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // --------------------------------------------------------------- neighbours
 struct BinRange {
   int y0, y1, z0, z1;
@@ -502,8 +516,17 @@ __global__ __launch_bounds__(256) void k_neighbours(Inputs in, Span sp, int R, c
     if (nh * (int64_t)sizeof(SortedHit) + nb * (int64_t)sizeof(int32_t) <= lds_bytes) {
       SortedHit* lh = reinterpret_cast<SortedHit*>(lds);
       int32_t* lb = reinterpret_cast<int32_t*>(lds + nh * sizeof(SortedHit));
-      for (int k = threadIdx.x; k < nh; k += blockDim.x) lh[k] = ws.sorted[h0 + k];
-      for (int k = threadIdx.x; k < nb; k += blockDim.x) lb[k] = ws.bins[b0 + k];
+      // global-to-LDS copies (no registers): lane j of a copy writes entry
+      // j of its destination; each wave takes every (blockDim/64)-th run of
+      // 64 entries
+      const int lane = threadIdx.x & 63;
+      for (int64_t base = threadIdx.x - lane; base < nh; base += blockDim.x)
+        if (base + lane < nh)
+          __builtin_amdgcn_global_load_lds((GlobalPtr)(ws.sorted + h0 + base + lane), (LdsPtr)(lh + base), 16, 0, 0);
+      for (int64_t base = threadIdx.x - lane; base < nb; base += blockDim.x)
+        if (base + lane < nb)
+          __builtin_amdgcn_global_load_lds((GlobalPtr)(ws.bins + b0 + base + lane), (LdsPtr)(lb + base), 4, 0, 0);
+      stage_wait();
       __syncthreads();
       S.on = true;
       S.hit0 = h0;
@@ -1140,9 +1163,6 @@ __device__ __forceinline__ int wave_max16(int v) {
 // than kStageBytes is searched in place.
 constexpr int kStageBytes = 7168;  // per wave: rows of up to about 290 hits
 
-typedef __attribute__((address_space(1))) void* GlobalPtr;
-typedef __attribute__((address_space(3))) void* LdsPtr;
-
 struct StageLayout {
   int off;   // ints between the 16-byte boundary and the row's first bin (0 or 2)
   int bch;   // 16-byte chunks of bin table
@@ -1188,13 +1208,6 @@ __device__ __forceinline__ void stage_row(int64_t i, int hit_base, int bin_half,
   }
 }
 
-// Wait for the wave's outstanding global memory operations (the LDS copies
-// among them: nothing else orders a later LDS read after them).
-__device__ __forceinline__ void stage_wait() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), other counters not waited
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
 
 // Staging state of a wave (row-synchronous form): the staged row's bin counts
 // and layout, and the second half of the header of the row the wave steps to
