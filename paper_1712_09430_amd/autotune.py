@@ -32,12 +32,20 @@ JOINT = {
     "tc_occupancy": [0, 5, 6, 8],
     "tc_waves_per_cu": [8, 12, 16, 20, 24, 32],
 }
+# The neighbour finder's row chunk, LDS budget and workgroup size, jointly
+# too: the chunk's staged rows must fit the budget, and the hits per chunk set
+# how many of a workgroup's lanes have work.
+NF_JOINT = {
+    "nf_rows": [1, 2, 4],
+    "nf_lds_kb": [8, 16, 24],
+    "nf_block": [128, 256],
+}
 # Then one coordinate at a time.
 SPACE = {
     "tc_xcd": [0, 1],
     "tc_block": [64, 128, 256],
     "bin_hits": [0.5, 1.0, 2.0, 4.0, 8.0],
-    "nf_rows": [2, 4, 8, 16, 32],
+    "nf_rows": [1, 2, 4, 8, 16, 32],
     "nf_lds_kb": [0, 16, 32, 48, 64],
     "nf_block": [64, 128, 256],
 }
@@ -164,6 +172,18 @@ def tune(tracker, hits, out, passes=2, log=print):
                 ms = time_config(tracker, hits, out, cand)
                 trials.append((cand, ms))
                 log(f"[autotune] sync={sync} occupancy={occ} waves/CU={waves}: {ms:.3f} ms")
+                if ms < best_ms * 0.99:
+                    best_ms, cur = ms, cand
+    base = dict(cur)
+    for rows in NF_JOINT["nf_rows"]:
+        for lds in NF_JOINT["nf_lds_kb"]:
+            for block in NF_JOINT["nf_block"]:
+                cand = dict(base, nf_rows=rows, nf_lds_kb=lds, nf_block=block)
+                if cand == cur:
+                    continue
+                ms = time_config(tracker, hits, out, cand)
+                trials.append((cand, ms))
+                log(f"[autotune] nf_rows={rows} nf_lds_kb={lds} nf_block={block}: {ms:.3f} ms")
                 if ms < best_ms * 0.99:
                     best_ms, cur = ms, cand
     for _ in range(passes):
