@@ -498,6 +498,30 @@ __global__ __launch_bounds__(256) void k_neighbours(Inputs in, Span sp, int R, c
   S.on = false;
   S.r_lo = max(c0 - 1, 0);
   S.r_hi = min(c1, R - 1);
+  // the rows' hits and bin tables are copied into LDS (global-to-LDS, no
+  // registers: lane j of a copy writes entry j of its destination; each wave
+  // takes every (blockDim/64)-th run of 64 entries) when they fit, issued
+  // before the row headers are read so that one wait and one barrier cover both
+  const int64_t h0 = a + rf[S.r_lo], h1 = a + rf[S.r_hi + 1];
+  const int64_t b0 = 2 * (h0 + (int64_t)s * R + S.r_lo);
+  const int64_t b1 = 2 * (h1 + (int64_t)s * R + S.r_hi + 1);
+  const int64_t nh = h1 - h0, nb = b1 - b0;
+  if (nh * (int64_t)sizeof(SortedHit) + nb * (int64_t)sizeof(int32_t) <= lds_bytes) {
+    SortedHit* lh = reinterpret_cast<SortedHit*>(lds);
+    int32_t* lb = reinterpret_cast<int32_t*>(lds + nh * sizeof(SortedHit));
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = threadIdx.x - lane; base < nh; base += blockDim.x)
+      if (base + lane < nh)
+        __builtin_amdgcn_global_load_lds((GlobalPtr)(ws.sorted + h0 + base + lane), (LdsPtr)(lh + base), 16, 0, 0);
+    for (int64_t base = threadIdx.x - lane; base < nb; base += blockDim.x)
+      if (base + lane < nb)
+        __builtin_amdgcn_global_load_lds((GlobalPtr)(ws.bins + b0 + base + lane), (LdsPtr)(lb + base), 4, 0, 0);
+    S.on = true;
+    S.hit0 = h0;
+    S.bin0 = b0;
+    S.hits = lh;
+    S.bins = lb;
+  }
   // row headers and row constants of the block's rows and their neighbours
   __shared__ RowHdr nf_hdr[kNfMaxRows + 2];
   __shared__ float4 nf_rowk[kNfMaxRows + 2];
@@ -507,34 +531,8 @@ __global__ __launch_bounds__(256) void k_neighbours(Inputs in, Span sp, int R, c
   }
   S.hdr = nf_hdr;
   S.rowk = nf_rowk;
+  if (S.on) stage_wait();
   __syncthreads();
-  {
-    const int64_t h0 = a + rf[S.r_lo], h1 = a + rf[S.r_hi + 1];
-    const int64_t b0 = 2 * (h0 + (int64_t)s * R + S.r_lo);
-    const int64_t b1 = 2 * (h1 + (int64_t)s * R + S.r_hi + 1);
-    const int64_t nh = h1 - h0, nb = b1 - b0;
-    if (nh * (int64_t)sizeof(SortedHit) + nb * (int64_t)sizeof(int32_t) <= lds_bytes) {
-      SortedHit* lh = reinterpret_cast<SortedHit*>(lds);
-      int32_t* lb = reinterpret_cast<int32_t*>(lds + nh * sizeof(SortedHit));
-      // global-to-LDS copies (no registers): lane j of a copy writes entry
-      // j of its destination; each wave takes every (blockDim/64)-th run of
-      // 64 entries
-      const int lane = threadIdx.x & 63;
-      for (int64_t base = threadIdx.x - lane; base < nh; base += blockDim.x)
-        if (base + lane < nh)
-          __builtin_amdgcn_global_load_lds((GlobalPtr)(ws.sorted + h0 + base + lane), (LdsPtr)(lh + base), 16, 0, 0);
-      for (int64_t base = threadIdx.x - lane; base < nb; base += blockDim.x)
-        if (base + lane < nb)
-          __builtin_amdgcn_global_load_lds((GlobalPtr)(ws.bins + b0 + base + lane), (LdsPtr)(lb + base), 4, 0, 0);
-      stage_wait();
-      __syncthreads();
-      S.on = true;
-      S.hit0 = h0;
-      S.bin0 = b0;
-      S.hits = lh;
-      S.bins = lb;
-    }
-  }
   if (S.on)
     nf_hits<true>(S.hits + (a + rf[c0] - S.hit0), n, a, s, R, rowk, c, ws, S, out_up, out_dn);
   else
