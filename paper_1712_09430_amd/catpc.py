@@ -104,6 +104,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        # torch first: its libraries load the HIP runtime bundled with them
+        # under the unversioned name, which a runtime loaded earlier under its
+        # versioned name (the library's own dependency) does not satisfy.  Two
+        # HIP runtimes in one process do not share the device (the second one
+        # reports none), so the library must bind to torch's, already loaded.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         st = ctypes.c_int32
         P = ctypes.POINTER
