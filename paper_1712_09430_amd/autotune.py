@@ -36,18 +36,18 @@ JOINT = {
 # too: the chunk's staged rows must fit the budget, and the hits per chunk set
 # how many of a workgroup's lanes have work.
 NF_JOINT = {
-    "nf_rows": [1, 2, 4],
-    "nf_lds_kb": [8, 16, 24],
-    "nf_block": [128, 256],
+    "nf_rows": [1, 2, 3, 4],
+    "nf_lds_kb": [8, 10, 12, 16, 24],
+    "nf_block": [128, 192, 256],
 }
 # Then one coordinate at a time.
 SPACE = {
     "tc_xcd": [0, 1],
     "tc_block": [64, 128, 256],
     "bin_hits": [0.5, 1.0, 2.0, 4.0, 8.0],
-    "nf_rows": [1, 2, 4, 8, 16, 32],
-    "nf_lds_kb": [0, 16, 32, 48, 64],
-    "nf_block": [64, 128, 256],
+    "nf_rows": [1, 2, 3, 4, 8, 16, 32],
+    "nf_lds_kb": [0, 10, 12, 14, 16, 32, 48, 64],
+    "nf_block": [64, 128, 192, 256],
 }
 
 

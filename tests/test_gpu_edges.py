@@ -161,6 +161,7 @@ TUNINGS = [
     {"bin_hits": 0.5, "nf_rows": 4, "nf_lds_kb": 64, "nf_block": 256},
     {"bin_hits": 64.0, "nf_rows": 1, "nf_lds_kb": 0, "nf_block": 64, "tc_sync": 1},
     {"bin_hits": 0.25, "nf_rows": 32, "nf_lds_kb": 8, "nf_block": 128, "use_graph": 0, "tc_sync": 1},
+    {"bin_hits": 0.5, "nf_rows": 3, "nf_lds_kb": 12, "nf_block": 192, "tc_sync": 1},
 ]
 
 
