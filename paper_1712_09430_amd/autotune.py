@@ -51,12 +51,15 @@ SPACE = {
 }
 
 
-# Serving: searched one coordinate at a time from the batch tuning.
+# Serving: searched one coordinate at a time from the batch tuning (one or a
+# few events per launch: sparser sectors per workgroup than in the batch, so
+# the neighbour finder's row chunk is searched again too).
 SERVE_SPACE = {
     "tc_sync": [0, 1],
     "tc_xcd": [0, 1],
     "tc_waves_per_cu": [4, 6, 8, 12, 16],
     "tc_block": [64, 128, 256],
+    "nf_rows": [2, 3, 4, 8, 16],
 }
 
 
