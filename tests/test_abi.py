@@ -2,6 +2,7 @@
 host-side argument validation (no GPU needed: every call below fails before
 touching the device)."""
 import ctypes
+import json
 import os
 import re
 import subprocess
@@ -152,13 +153,13 @@ def test_one_hip_runtime_when_the_library_loads_first():
     """Loading the library before anything imports torch still leaves one
     HIP runtime in the process (torch's): a second runtime would not see the
     device.  Checked in a fresh process, from its memory map."""
-    code = ("import os, sys; sys.path.insert(0, %r)\n"
+    code = ("import json, os, sys; sys.path.insert(0, %r)\n"
             "from paper_1712_09430_amd import catpc as C\n"
             "C.lib()\n"
             "import torch\n"
             "m = open('/proc/%%d/maps' %% os.getpid()).read().splitlines()\n"
-            "print(sorted(set(l.split()[-1] for l in m if 'libamdhip64' in l)))\n") % ROOT
+            "print(json.dumps(sorted(set(l.split()[-1] for l in m if 'libamdhip64' in l))))\n") % ROOT
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
-    libs = eval(out.stdout.strip().splitlines()[-1])
+    libs = json.loads(out.stdout.strip().splitlines()[-1])
     assert len(libs) == 1, libs
