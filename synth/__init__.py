@@ -235,19 +235,19 @@ def sector_workload(seed=1, n_tracks=200, truth=False, **kw):
     kw.setdefault("eta", (0.0, 0.9))
     kw.setdefault("phi", (a0 - math.radians(10.0), a0 + math.radians(10.0)))
     ev = generate_event(seed, n_tracks, 0, sectors=(0, 1), truth=truth, **kw)
-    return Batch([(0, 0, ev)], bz=kw.get("bz", BZ))
+    return Batch([(0, 0, ev)], n_rows=kw.get("n_rows", N_ROWS), bz=kw.get("bz", BZ))
 
 
 def tracks_workload(tracks, sector=0, seed=1, truth=True, **kw):
     """One sector from an explicit track table (see generate_event)."""
     ev = generate_event(seed, 0, 0, sectors=(sector, 1), truth=truth, tracks=tracks, **kw)
-    return Batch([(0, sector, ev)], bz=kw.get("bz", BZ))
+    return Batch([(0, sector, ev)], n_rows=kw.get("n_rows", N_ROWS), bz=kw.get("bz", BZ))
 
 
 def event_workload(seed=1, n_tracks=10000, truth=False, **kw):
     """A full event: n_tracks primaries over all 36 sectors."""
     ev = generate_event(seed, n_tracks, 0, sectors=(0, N_SECTORS), truth=truth, **kw)
-    return Batch([(0, 0, ev)], bz=kw.get("bz", BZ))
+    return Batch([(0, 0, ev)], n_rows=kw.get("n_rows", N_ROWS), bz=kw.get("bz", BZ))
 
 
 def multiplicities(seed, n_events, lo=20.0, hi=1.0e4):
@@ -260,7 +260,7 @@ def event_pool(seed=2, n_events=64, lo=20.0, hi=1.0e4, **kw):
     mult = multiplicities(seed, n_events, lo, hi)
     from concurrent.futures import ThreadPoolExecutor
     work = lambda i: Batch([(i, 0, generate_event(seed, mult[i], i, sectors=(0, N_SECTORS), **kw))],
-                           bz=kw.get("bz", BZ))
+                           n_rows=kw.get("n_rows", N_ROWS), bz=kw.get("bz", BZ))
     with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         return list(ex.map(work, range(n_events)))
 
@@ -274,6 +274,6 @@ def batch_workload(seed=1, n_events=64, lo=20.0, hi=1.0e4, truth=False, first_ev
     with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         evs = list(ex.map(work, range(len(mult))))
     parts = [(first_event + i, 0, ev) for i, ev in enumerate(evs)]
-    b = Batch(parts, bz=kw.get("bz", BZ))
+    b = Batch(parts, n_rows=kw.get("n_rows", N_ROWS), bz=kw.get("bz", BZ))
     b.multiplicity = mult
     return b

@@ -107,6 +107,32 @@ def test_noise_free_helices_are_recovered_from_their_own_seed(q, pt):
     assert abs(l1 - l2) <= 2e-2 * max(abs(l1), abs(l2)) + 2e-8, (l1, l2)
 
 
+@pytest.mark.parametrize("n_rows", [40, 320])
+@pytest.mark.parametrize("q", [1, -1])
+def test_noise_free_helices_on_other_row_counts(n_rows, q):
+    """The same pin on other pad-row geometries (n_rows planes between the
+    same first and last radii: rows four times sparser, or twice as dense):
+    a track crossing every row is one valid tracklet holding all its hits,
+    its transverse parameters recover the truth within the gate, z and tan
+    lambda are exact at eta = 0 and within the gate at eta = 0.45."""
+    for pt in (1.0, 3.0, 10.0):
+        phi = _phi_for(q, pt)
+        for eta in (0.0, 0.45):
+            b, s, o = _fit(q, pt, eta, phi, n_rows=n_rows)
+            assert len(b.row_x) == n_rows and b.n_hits == n_rows
+            assert len(o["start"]) == 1
+            assert o["n_hits"][0] == b.n_hits and o["flags"][0] == oracle.VALID
+            assert o["first_row"][0] == 0 and o["last_row"][0] == n_rows - 1
+            truth = _truth(s, o, 0, q, pt, eta)
+            d = o["param"][0] - truth
+            _transverse_ok(d, truth)
+            if eta == 0.0:
+                assert d[1] == 0.0 and d[3] == 0.0
+            else:
+                assert abs(d[1]) <= TOL_Y, ("z", d[1])
+                assert abs(d[3]) <= TOL_REL * max(abs(truth[3]), 1.0), ("tan lambda", d[3])
+
+
 def test_inward_pass_recovers_the_truth():
     """A dead pad row (19) splits the seeding: the hits next to it get no
     links (the neighbour finder needs both adjacent rows), so one seed starts

@@ -88,3 +88,18 @@ def test_determinism():
     c = synth.sector_workload(seed=8)
     assert np.array_equal(a.y, b.y) and np.array_equal(a.row, b.row)
     assert a.n_hits != c.n_hits or not np.array_equal(a.y, c.y)
+
+
+def test_workloads_keep_the_row_count_they_are_given():
+    """Every workload helper builds its row planes for the n_rows the events
+    were generated with (the row values stay below it)."""
+    import synth
+    for b in (synth.sector_workload(seed=1, n_tracks=20, n_rows=64),
+              synth.tracks_workload({"q": [1], "pt": [1.0], "eta": [0.2], "phi0": [synth.sector_alpha(0)]},
+                                    n_rows=30, sigma=0.0, noise_frac=0.0),
+              synth.event_workload(seed=1, n_tracks=30, n_rows=17),
+              synth.batch_workload(seed=1, n_events=2, n_rows=40),
+              synth.event_pool(seed=1, n_events=2, n_rows=25)[1]):
+        n = len(b.row_x)
+        assert n == b.n_rows and int(b.row.max()) < n and n in (64, 30, 17, 40, 25)
+        assert np.all(np.diff(b.row_x) > 0)
