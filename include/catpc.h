@@ -218,6 +218,9 @@ size_t catpc_workspace_bytes(int32_t n_rows, int64_t max_hits, int32_t max_secto
  * parameters), CATPC_E_HIP if allocation fails; *out is NULL on failure. */
 catpc_status catpc_create(const catpc_geometry* geom, const catpc_params* params, int64_t max_hits,
                           int32_t max_sectors, catpc_ctx** out);
+/* Free the tracker's device and pinned host memory and its captured graphs
+ * (a NULL ctx is ignored).  Work enqueued with ctx must have completed; the
+ * caller's output buffers are not touched. */
 void catpc_destroy(catpc_ctx* ctx);
 
 /* Frame of sector `sector_id` (host call, no device needed): its rotation
@@ -239,8 +242,20 @@ catpc_status catpc_sector_frame(const catpc_geometry* geom, int32_t sector_id, d
 catpc_status catpc_to_global(const catpc_geometry* geom, int32_t sector_id, int64_t n, const float* x,
                              const float* param, double* out);
 
+/* Replace the method parameters (field, cluster errors, windows, cuts,
+ * limits, precision form) for later track calls; a captured graph made with
+ * other parameters is captured again at the next batched call.
+ * CATPC_E_INVALID for a NULL argument or a parameter out of range (cluster
+ * errors <= 0, a negative window, cut, miss limit or hit count, precision
+ * not 0-2); the previous parameters then stay. */
 catpc_status catpc_set_params(catpc_ctx* ctx, const catpc_params* params);
+/* Replace the launch shape for later calls (results never depend on it); a
+ * graph captured with another shape is captured again.  CATPC_E_INVALID for a
+ * NULL argument or a field out of its documented range; the previous tuning
+ * then stays. */
 catpc_status catpc_set_tuning(catpc_ctx* ctx, const catpc_tuning* tuning);
+/* Copy the tracker's current launch shape to *tuning (CATPC_E_INVALID for a
+ * NULL argument). */
 catpc_status catpc_get_tuning(const catpc_ctx* ctx, catpc_tuning* tuning);
 
 /* Batched form: the whole hot path (row index and grid build, neighbour
