@@ -87,6 +87,15 @@ def test_batch64_every_sector_bit_exact_and_global_properties():
     assert np.array_equal((rh >= 0).sum(1), trk["n_hits"])
 
 
+def test_second_batch64_seed_every_sector_bit_exact():
+    """A second 64-event batch (other multiplicities and tracks, seed 2) in
+    the benchmark's launch configuration, every sector against the oracle."""
+    b = synth.batch_workload(seed=2, n_events=64)
+    tr, hits, out, n, p = run_bench_config(b)
+    assert b.n_hits > 5_000_000 and n > 50_000
+    check_sectors(b, out, n, p, range(b.n_sectors))
+
+
 def test_batch64_refit_and_merge_every_sector_bit_exact():
     """Selection, refit and segment merging after the bench configuration's
     track call on the 64-event batch: the fits and the links of every sector
